@@ -1,0 +1,128 @@
+/*
+ * lddmm.h -- C ABI of liblddmm, landmark geodesic shooting on MI355X (gfx950).
+ *
+ * The library computes, on one GPU, the objects of landmark matching by
+ * geodesic shooting (paper Sec. 2.1):
+ *
+ *   kernel       g_ij = exp(-|q_i - q_j|^2 / (2 sigma^2))
+ *   Hamiltonian  H(q,p) = 1/2 sum_ij g_ij p_i . p_j                   (eq. 1)
+ *   flow         dq/dt = dH/dp, dp/dt = -dH/dq, explicit Euler with
+ *                dt = 1/T over t in [0,1], q and p updated together   (eq. 2; Alg. 1)
+ *   loss         L(p0) = H(q0,p0) + lambda sum_i |q_i(1) - x_i|^2     (eq. 3)
+ *   gradient     dL/dp0 by the exact adjoint of the discrete Euler map,
+ *                run backwards in time                                (Alg. 1)
+ *   solver       L-BFGS over p0                                       (Sec. 2.1; Alg. 1)
+ *
+ * Conventions shared by every call:
+ *   - Point sets (q0, p0, target, q1, p1, grad) are DEVICE pointers to [n][3]
+ *     row-major FP64 arrays owned by the caller.  They must not overlap one
+ *     another.  Results are always FP64, whatever the pair-sum precision.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call enqueues its work on that stream and returns without
+ *     waiting; outputs are valid once the stream has reached that point.
+ *   - Device scalars (loss, H0) are written by the GPU, in stream order.
+ *   - Functions never throw and never abort.  Invalid arguments are reported
+ *     synchronously (LDDMM_EINVAL) before any work is enqueued; a detail
+ *     string is then available from lddmm_last_error().  A HIP runtime
+ *     failure is LDDMM_EDEVICE.  Non-finite intermediates are flagged on the
+ *     device and reported by lddmm_ctx_check().
+ *   - A context serialises its calls: one context must not be used from two
+ *     threads at once, nor on two streams whose work overlaps, because every
+ *     call reuses the context's workspace.
+ */
+#ifndef LDDMM_H
+#define LDDMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LDDMM_OK = 0,
+  LDDMM_ENOTCONV = 1,      /* solver stopped without meeting its tolerance; result written */
+  LDDMM_EINVAL = -1,       /* invalid argument */
+  LDDMM_ENOMEM = -2,       /* device allocation failed */
+  LDDMM_EDEVICE = -3,      /* HIP runtime error */
+  LDDMM_ENONFINITE = -4,   /* NaN or Inf met on the device */
+  LDDMM_EBUSY = -5         /* result not ready yet */
+} lddmm_status;
+
+/* Precision of the O(N^2) pair sums.  State, Euler updates, H, the loss and
+ * the optimiser are FP64 in every mode. */
+typedef enum {
+  LDDMM_FP32 = 0,          /* FP32 pair terms, one running FP32 sum per wave */
+  LDDMM_FP32_COMP = 1,     /* FP32 pair terms, FP32 sums of 64 pairs folded into FP64 */
+  LDDMM_FP64 = 2           /* FP64 throughout */
+} lddmm_precision;
+
+typedef struct {
+  int32_t n;               /* landmarks, >= 1 */
+  int32_t T;               /* Euler steps, >= 1 (dt = 1/T) */
+  double sigma;            /* Gaussian kernel width (standard deviation), > 0 */
+  double lambda;           /* mismatch weight, >= 0 */
+  int32_t precision;       /* lddmm_precision */
+  int32_t ckpt_every;      /* 0: keep the whole trajectory; s > 0: keep every
+                              s-th FP64 state and recompute each segment of s
+                              steps before its backward pass (same results) */
+} lddmm_params;
+
+typedef struct lddmm_ctx lddmm_ctx;
+
+/* A context binds one GPU and owns a device workspace (trajectory, adjoint
+ * state, partial sums), grown on demand and reused across calls.
+ * device: HIP device ordinal.  *out receives the context.
+ * Errors: EINVAL (null out, bad device), EDEVICE. */
+lddmm_status lddmm_ctx_create(int device, lddmm_ctx** out);
+
+/* Waits for the context's pending work, frees the workspace and the context.
+ * NULL is accepted. */
+lddmm_status lddmm_ctx_destroy(lddmm_ctx* ctx);
+
+/* Device workspace, in bytes, that a call with *params needs.  Pure host
+ * computation.  Errors: EINVAL. */
+lddmm_status lddmm_workspace_size(const lddmm_params* params, size_t* bytes);
+
+/* Forward shooting (Alg. 1, forward loop; eq. 2): integrates (q, p) from
+ * (q0, p0) over T Euler steps.
+ *   q0, p0 : in,  [n][3] device FP64
+ *   q1, p1 : out, [n][3] device FP64, q(1) and p(1); either may be NULL
+ *   H0     : out, device FP64 scalar H(q0,p0) (eq. 1); may be NULL
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+lddmm_status lddmm_shoot_forward(lddmm_ctx* ctx, const lddmm_params* params, const double* q0,
+                                 const double* p0, double* q1, double* p1, double* H0,
+                                 void* stream);
+
+/* Loss and gradient (Alg. 1 ComputeGradient; eq. 3): one forward pass, the
+ * loss, and one adjoint pass.
+ *   q0, p0, target : in,  [n][3] device FP64 (template, momentum, target x)
+ *   out3           : out, 3 device FP64 scalars {L, H(q0,p0), sum_i |q_i(1)-x_i|^2}
+ *   grad           : out, [n][3] device FP64, dL/dp0
+ *   q1             : out, [n][3] device FP64 q(1); may be NULL
+ * Errors: EINVAL, ENOMEM, EDEVICE. */
+lddmm_status lddmm_shoot_grad(lddmm_ctx* ctx, const lddmm_params* params, const double* q0,
+                              const double* p0, const double* target, double* out3,
+                              double* grad, double* q1, void* stream);
+
+/* Waits for the context's work on `stream` and reports whether any call
+ * since the last check produced a non-finite loss (then ENONFINITE, and the
+ * flag is cleared).  Errors: EINVAL, EDEVICE. */
+lddmm_status lddmm_ctx_check(lddmm_ctx* ctx, void* stream);
+
+/* Static description of a status code; never NULL. */
+const char* lddmm_status_string(lddmm_status status);
+
+/* Detail of the last error reported by a call on ctx from this thread
+ * (empty string if none); with ctx == NULL, of the last context-free error. */
+const char* lddmm_last_error(lddmm_ctx* ctx);
+
+/* Library version, "major.minor.patch". */
+const char* lddmm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDDMM_H */

@@ -48,6 +48,11 @@ def lib():
         L.oracle_pair_forward.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp, ctypes.c_int]
         L.oracle_pair_adjoint.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp,
                                           ctypes.c_int]
+        _ip = ctypes.POINTER(ctypes.c_int)
+        L.oracle_pair_forward_rows.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _ip,
+                                               ctypes.c_int, _dp, _dp]
+        L.oracle_pair_adjoint_rows.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp, _dp,
+                                               _ip, ctypes.c_int, _dp, _dp]
         L.oracle_hamiltonian.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, ctypes.c_int]
         L.oracle_hamiltonian.restype = ctypes.c_double
         L.oracle_shoot_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
@@ -97,6 +102,30 @@ def pair_adjoint(q, p, a, b, sigma: float, compensated: bool = False):
     A, B = np.empty_like(q), np.empty_like(q)
     lib().oracle_pair_adjoint(q.shape[0], float(sigma), _p(q), _p(p), _p(a), _p(b), _p(A), _p(B),
                               int(compensated))
+    return A, B
+
+
+def _rows(rows) -> np.ndarray:
+    return np.ascontiguousarray(rows, dtype=np.int32)
+
+
+def pair_forward_rows(q, p, sigma: float, rows):
+    """(Hq, Hp) for the listed rows only (each summed over all j)."""
+    q, p, rows = _in(q), _in(p), _rows(rows)
+    Hq, Hp = np.empty((len(rows), 3)), np.empty((len(rows), 3))
+    lib().oracle_pair_forward_rows(q.shape[0], float(sigma), _p(q), _p(p),
+                                   rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(rows),
+                                   _p(Hq), _p(Hp))
+    return Hq, Hp
+
+
+def pair_adjoint_rows(q, p, a, b, sigma: float, rows):
+    """(A, B) for the listed rows only (each summed over all j)."""
+    q, p, a, b, rows = _in(q), _in(p), _in(a), _in(b), _rows(rows)
+    A, B = np.empty((len(rows), 3)), np.empty((len(rows), 3))
+    lib().oracle_pair_adjoint_rows(q.shape[0], float(sigma), _p(q), _p(p), _p(a), _p(b),
+                                   rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), len(rows),
+                                   _p(A), _p(B))
     return A, B
 
 

@@ -119,32 +119,44 @@ typedef struct {
     double *Hq, *Hp;
 } fwd_ctx;
 
-static void fwd_rows(void *v, int i0, int i1) {
-    fwd_ctx *k = (fwd_ctx *)v;
+/* row i of the forward sums, written to hq[0..2], hp[0..2] */
+static void fwd_row(const fwd_ctx *k, int i, double *hq_out, double *hp_out) {
     const double c = 1.0 / (k->sigma * k->sigma);
-    for (int i = i0; i < i1; ++i) {
-        const double *qi = k->q + 3 * i, *pi = k->p + 3 * i;
-        acc_t hp[3] = {{0, 0}, {0, 0}, {0, 0}}, hq[3] = {{0, 0}, {0, 0}, {0, 0}};
-        for (int j = 0; j < k->n; ++j) {
-            const double *qj = k->q + 3 * j, *pj = k->p + 3 * j;
-            double g = gauss(qi, qj, k->sigma);
-            double s = pi[0] * pj[0] + pi[1] * pj[1] + pi[2] * pj[2];
-            for (int d = 0; d < 3; ++d) {
-                acc_add(&hp[d], g * pj[d], k->comp);
-                acc_add(&hq[d], g * s * (qi[d] - qj[d]), k->comp);
-            }
-        }
+    const double *qi = k->q + 3 * i, *pi = k->p + 3 * i;
+    acc_t hp[3] = {{0, 0}, {0, 0}, {0, 0}}, hq[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int j = 0; j < k->n; ++j) {
+        const double *qj = k->q + 3 * j, *pj = k->p + 3 * j;
+        double g = gauss(qi, qj, k->sigma);
+        double s = pi[0] * pj[0] + pi[1] * pj[1] + pi[2] * pj[2];
         for (int d = 0; d < 3; ++d) {
-            k->Hp[3 * i + d] = acc_get(&hp[d]);
-            k->Hq[3 * i + d] = -c * acc_get(&hq[d]);
+            acc_add(&hp[d], g * pj[d], k->comp);
+            acc_add(&hq[d], g * s * (qi[d] - qj[d]), k->comp);
         }
     }
+    for (int d = 0; d < 3; ++d) {
+        hp_out[d] = acc_get(&hp[d]);
+        hq_out[d] = -c * acc_get(&hq[d]);
+    }
+}
+
+static void fwd_rows(void *v, int i0, int i1) {
+    fwd_ctx *k = (fwd_ctx *)v;
+    for (int i = i0; i < i1; ++i) fwd_row(k, i, k->Hq + 3 * i, k->Hp + 3 * i);
 }
 
 void oracle_pair_forward(int n, double sigma, const double *q, const double *p,
                          double *Hq, double *Hp, int compensated) {
     fwd_ctx k = {n, compensated, sigma, q, p, Hq, Hp};
     for_rows(n, fwd_rows, &k);
+}
+
+/* The same sums for a listed subset of rows only (all j), for checking
+ * sampled outputs of problems too large for the full O(N^2) oracle.
+ * Outputs are [nrows][3]. */
+void oracle_pair_forward_rows(int n, double sigma, const double *q, const double *p,
+                              const int *rows, int nrows, double *Hq, double *Hp) {
+    fwd_ctx k = {n, 0, sigma, q, p, NULL, NULL};
+    for (int r = 0; r < nrows; ++r) fwd_row(&k, rows[r], Hq + 3 * r, Hp + 3 * r);
 }
 
 /* H(q,p) = 1/2 sum_ij g_ij p_i.p_j  (eq. 1), summed row by row */
@@ -185,39 +197,49 @@ typedef struct {
     double *A, *B;
 } adj_ctx;
 
-static void adj_rows(void *v, int i0, int i1) {
-    adj_ctx *k = (adj_ctx *)v;
+/* row i of the adjoint sums, written to A_out[0..2], B_out[0..2] */
+static void adj_row(const adj_ctx *k, int i, double *A_out, double *B_out) {
     const double c = 1.0 / (k->sigma * k->sigma);
-    for (int i = i0; i < i1; ++i) {
-        const double *qi = k->q + 3 * i, *pi = k->p + 3 * i;
-        const double *ai = k->a + 3 * i, *bi = k->b + 3 * i;
-        acc_t sa[3] = {{0, 0}, {0, 0}, {0, 0}}, sb[3] = {{0, 0}, {0, 0}, {0, 0}};
-        for (int j = 0; j < k->n; ++j) {
-            const double *qj = k->q + 3 * j, *pj = k->p + 3 * j;
-            const double *aj = k->a + 3 * j, *bj = k->b + 3 * j;
-            double g = gauss(qi, qj, k->sigma);
-            double D[3], db[3];
-            for (int d = 0; d < 3; ++d) { D[d] = qi[d] - qj[d]; db[d] = bi[d] - bj[d]; }
-            double s = pi[0] * pj[0] + pi[1] * pj[1] + pi[2] * pj[2];
-            double e = D[0] * db[0] + D[1] * db[1] + D[2] * db[2];
-            double pij = ai[0] * pj[0] + ai[1] * pj[1] + ai[2] * pj[2]
-                       + pi[0] * aj[0] + pi[1] * aj[1] + pi[2] * aj[2];
-            for (int d = 0; d < 3; ++d) {
-                acc_add(&sa[d], g * (s * db[d] - (pij + c * s * e) * D[d]), k->comp);
-                acc_add(&sb[d], g * (aj[d] + c * e * pj[d]), k->comp);
-            }
-        }
+    const double *qi = k->q + 3 * i, *pi = k->p + 3 * i;
+    const double *ai = k->a + 3 * i, *bi = k->b + 3 * i;
+    acc_t sa[3] = {{0, 0}, {0, 0}, {0, 0}}, sb[3] = {{0, 0}, {0, 0}, {0, 0}};
+    for (int j = 0; j < k->n; ++j) {
+        const double *qj = k->q + 3 * j, *pj = k->p + 3 * j;
+        const double *aj = k->a + 3 * j, *bj = k->b + 3 * j;
+        double g = gauss(qi, qj, k->sigma);
+        double D[3], db[3];
+        for (int d = 0; d < 3; ++d) { D[d] = qi[d] - qj[d]; db[d] = bi[d] - bj[d]; }
+        double s = pi[0] * pj[0] + pi[1] * pj[1] + pi[2] * pj[2];
+        double e = D[0] * db[0] + D[1] * db[1] + D[2] * db[2];
+        double pij = ai[0] * pj[0] + ai[1] * pj[1] + ai[2] * pj[2]
+                   + pi[0] * aj[0] + pi[1] * aj[1] + pi[2] * aj[2];
         for (int d = 0; d < 3; ++d) {
-            k->A[3 * i + d] = c * acc_get(&sa[d]);
-            k->B[3 * i + d] = acc_get(&sb[d]);
+            acc_add(&sa[d], g * (s * db[d] - (pij + c * s * e) * D[d]), k->comp);
+            acc_add(&sb[d], g * (aj[d] + c * e * pj[d]), k->comp);
         }
     }
+    for (int d = 0; d < 3; ++d) {
+        A_out[d] = c * acc_get(&sa[d]);
+        B_out[d] = acc_get(&sb[d]);
+    }
+}
+
+static void adj_rows(void *v, int i0, int i1) {
+    adj_ctx *k = (adj_ctx *)v;
+    for (int i = i0; i < i1; ++i) adj_row(k, i, k->A + 3 * i, k->B + 3 * i);
 }
 
 void oracle_pair_adjoint(int n, double sigma, const double *q, const double *p,
                          const double *a, const double *b, double *A, double *B, int compensated) {
     adj_ctx k = {n, compensated, sigma, q, p, a, b, A, B};
     for_rows(n, adj_rows, &k);
+}
+
+void oracle_pair_adjoint_rows(int n, double sigma, const double *q, const double *p,
+                              const double *a, const double *b, const int *rows, int nrows,
+                              double *A, double *B) {
+    adj_ctx k = {n, 0, sigma, q, p, a, b, NULL, NULL};
+    for (int r = 0; r < nrows; ++r) adj_row(&k, rows[r], A + 3 * r, B + 3 * r);
 }
 
 /* ------------------------------------------------------------------------ */

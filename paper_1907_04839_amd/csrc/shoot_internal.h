@@ -1,0 +1,92 @@
+// Internal interface between the C-ABI layer (lddmm_api.cpp) and the HIP
+// kernels (shoot_kernels.hip).  Not installed; callers use include/lddmm.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace lddmm {
+
+// Precision of the pair sums (the FP64 state, loss and optimiser are FP64 in
+// every mode).
+enum Mode : int { kFP32 = 0, kFP32Comp = 1, kFP64 = 2 };
+
+// Work decomposition of one N x N pair sum.  Landmark i is owned by lane
+// (i mod 64) of a wave of i-block ib = i / 64; the j range is split into S
+// chunks (one workgroup each) and, inside a workgroup, over W waves.
+// Partial sums of different chunks are combined in chunk order.
+struct Plan {
+  int n;        // landmarks
+  int nb;       // i-blocks of 64
+  int S;        // j-chunks (workgroups) per i-block
+  int W;        // waves per workgroup
+  int chunk;    // j per workgroup
+  int wchunk;   // j per wave
+};
+
+Plan make_plan(int n, int target_waves);
+
+// Coordinates enter the pair kernels pre-scaled by k = sqrt(log2(e) / (2 sigma^2)),
+// so that the kernel value is exp2(-|k q_i - k q_j|^2).
+struct Scales {
+  double k;         // coordinate pre-scale
+  double hq;        // Hq = hq * sum g s (kq_i - kq_j)           = -(c / k)
+  double adj_a;     // A  = adj_a * (A1 / kappa - A2)            =  c / k
+  double kappa;     // 2 ln 2 = c / k^2 (independent of sigma)
+  double bscale;    // adjoint record stores b_hat = bscale * b = kappa k b
+  double dt;
+};
+
+Scales make_scales(double sigma, int T);
+
+// Arguments of one forward Euler step (pair sums + update).
+struct FwdArgs {
+  int n, nb, S, chunk, wchunk;
+  Scales sc;
+  const void* rec_t;    // point records at step t (k q, p)
+  void* rec_t1;         // point records at step t+1 (written)
+  double* st;           // FP64 state [6][n]: q (3 rows) then p (3 rows), centred
+  double* hp0;          // [3][n]: Hp(q0,p0) (written at t == 0, else null)
+  double* h0_part;      // [nb]: per i-block sum p0.Hp0 (t == 0, else null)
+  double* ckpt;         // [6][n]: copy of the new state (null unless a checkpoint)
+  void* partial;        // [S][6][n] partial sums when S > 1
+};
+
+// Arguments of one backward (adjoint) Euler step.
+struct AdjArgs {
+  int n, nb, S, chunk, wchunk;
+  Scales sc;
+  const void* rec_t;    // point records at step t (k q, p)
+  const void* arec;     // adjoint records (a, b_hat) entering the step
+  void* arec_next;      // adjoint records leaving the step (written)
+  double* ad;           // FP64 adjoint state [6][n]: a (3 rows) then b (3 rows)
+  const double* hp0;    // [3][n] Hp(q0,p0)
+  double* grad;         // [n][3] gradient, written at t == 0 (else null)
+  void* partial;        // [S][9][n] partial sums when S > 1
+};
+
+// Size in bytes of one point record and one partial-sum element.
+size_t rec_bytes(int mode);
+size_t acc_bytes(int mode);
+
+hipError_t launch_centroid(const double* q0, int n, double* cen, hipStream_t s);
+hipError_t launch_stage(int mode, int n, const double* q0, const double* p0, const double* x,
+                        const double* cen, double k, double* st, double* xc, void* rec0,
+                        hipStream_t s);
+hipError_t launch_restore(int mode, int n, const double* ckpt, double k, double* st, void* rec,
+                          hipStream_t s);
+hipError_t launch_fwd_step(int mode, const Plan& p, const FwdArgs& a, hipStream_t s);
+hipError_t launch_adj_step(int mode, const Plan& p, const AdjArgs& a, hipStream_t s);
+// Loss and terminal adjoint: L = H0 + lambda |q(1) - x|^2, a = 2 lambda (q(1) - x), b = 0.
+// out3 = {loss, H0, mismatch}; q1/p1 (optional) receive the final state, uncentred, [n][3].
+hipError_t launch_loss(int mode, int n, int nb, double lambda, double bscale, const double* st,
+                       const double* xc, const double* cen, const double* h0_part, double* ad,
+                       void* arec0, double* out3, double* q1, double* p1, int* flag,
+                       hipStream_t s);
+// Forward-only epilogue: writes H0 (device scalar) and the final state.
+hipError_t launch_forward_out(int n, int nb, const double* st, const double* cen,
+                              const double* h0_part, double* H0, double* q1, double* p1,
+                              hipStream_t s);
+
+}  // namespace lddmm

@@ -1,0 +1,187 @@
+"""Python binding of liblddmm (ctypes): argument marshalling only.
+
+Every step of the computation runs in the HIP kernels of ``liblddmm.so``;
+PyTorch provides device memory and the current stream.  There is no CPU
+fallback: if the library or a GPU is missing, calls raise.
+
+Names mirror ``include/lddmm.h``.  Point sets are float64 CUDA tensors of
+shape [N, 3] (contiguous).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # first: liblddmm then binds to the HIP runtime torch has loaded
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblddmm.so")
+
+OK, ENOTCONV, EINVAL, ENOMEM, EDEVICE, ENONFINITE, EBUSY = 0, 1, -1, -2, -3, -4, -5
+FP32, FP32_COMP, FP64 = 0, 1, 2
+PRECISIONS = {"fp32": FP32, "fp32c": FP32_COMP, "fp64": FP64}
+
+_vp = ctypes.c_void_p
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("T", ctypes.c_int32), ("sigma", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("ckpt_every", ctypes.c_int32)]
+
+
+class LddmmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load liblddmm.so (built in-tree by ``paper_1907_04839_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m "
+                               "paper_1907_04839_amd.build or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        L.lddmm_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(_vp)]
+        L.lddmm_ctx_destroy.argtypes = [_vp]
+        L.lddmm_workspace_size.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
+        L.lddmm_shoot_forward.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp]
+        L.lddmm_shoot_grad.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.lddmm_ctx_check.argtypes = [_vp, _vp]
+        L.lddmm_status_string.argtypes = [ctypes.c_int]
+        L.lddmm_status_string.restype = ctypes.c_char_p
+        L.lddmm_last_error.argtypes = [_vp]
+        L.lddmm_last_error.restype = ctypes.c_char_p
+        L.lddmm_version.restype = ctypes.c_char_p
+        for f in ("lddmm_ctx_create", "lddmm_ctx_destroy", "lddmm_workspace_size",
+                  "lddmm_shoot_forward", "lddmm_shoot_grad", "lddmm_ctx_check"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, ctx=None, allow=(OK,)) -> int:
+    if rc in allow:
+        return rc
+    L = lib()
+    detail = L.lddmm_last_error(ctx).decode() or L.lddmm_status_string(rc).decode()
+    raise LddmmError(rc, detail)
+
+
+def make_params(n: int, T: int, sigma: float, lam: float, precision="fp32c",
+                ckpt_every: int = 0) -> Params:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return Params(int(n), int(T), float(sigma), float(lam), prec, int(ckpt_every))
+
+
+def workspace_size(params: Params) -> int:
+    b = ctypes.c_size_t(0)
+    _check(lib().lddmm_workspace_size(ctypes.byref(params), ctypes.byref(b)))
+    return int(b.value)
+
+
+def _pts(t: torch.Tensor, name: str, n: int) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float64 or tuple(t.shape) != (n, 3) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 [{n}, 3] tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+@dataclass
+class GradResult:
+    loss: torch.Tensor       # device scalar
+    H0: torch.Tensor         # device scalar
+    mismatch: torch.Tensor   # device scalar, sum |q(1) - x|^2
+    grad: torch.Tensor       # [N,3]
+    q1: torch.Tensor | None
+
+
+class Context:
+    """One GPU and its reusable device workspace (``lddmm_ctx``)."""
+
+    def __init__(self, device: int | None = None):
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = _vp()
+        _check(lib().lddmm_ctx_create(self.device, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lddmm_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- calls -------------------------------------------------------------
+    def shoot_forward(self, q0: torch.Tensor, p0: torch.Tensor, T: int, sigma: float,
+                      precision="fp32c", stream=None):
+        """Forward Euler flow (Alg. 1 forward loop).  Returns (q1, p1, H0)."""
+        n = q0.shape[0]
+        prm = make_params(n, T, sigma, 0.0, precision)
+        q1 = torch.empty_like(q0)
+        p1 = torch.empty_like(q0)
+        H0 = torch.empty((), dtype=torch.float64, device=q0.device)
+        _check(lib().lddmm_shoot_forward(self._h, ctypes.byref(prm), _pts(q0, "q0", n),
+                                         _pts(p0, "p0", n), q1.data_ptr(), p1.data_ptr(),
+                                         H0.data_ptr(), _stream(stream)), self._h)
+        return q1, p1, H0
+
+    def shoot_grad(self, q0: torch.Tensor, p0: torch.Tensor, target: torch.Tensor, T: int,
+                   sigma: float, lam: float, precision="fp32c", ckpt_every: int = 0,
+                   want_q1: bool = True, stream=None, out: dict | None = None) -> GradResult:
+        """Loss of eq. 3 and its gradient w.r.t. p0 (Alg. 1 ComputeGradient).
+
+        ``out`` may hold preallocated ``grad`` [N,3], ``out3`` [3] and ``q1``.
+        """
+        n = q0.shape[0]
+        prm = make_params(n, T, sigma, lam, precision, ckpt_every)
+        out = out or {}
+        grad = out.get("grad")
+        if grad is None:
+            grad = torch.empty_like(q0)
+        out3 = out.get("out3")
+        if out3 is None:
+            out3 = torch.empty(3, dtype=torch.float64, device=q0.device)
+        q1 = out.get("q1") if want_q1 else None
+        if want_q1 and q1 is None:
+            q1 = torch.empty_like(q0)
+        _check(lib().lddmm_shoot_grad(self._h, ctypes.byref(prm), _pts(q0, "q0", n),
+                                      _pts(p0, "p0", n), _pts(target, "target", n),
+                                      out3.data_ptr(), _pts(grad, "grad", n),
+                                      q1.data_ptr() if q1 is not None else None,
+                                      _stream(stream)), self._h)
+        return GradResult(out3[0], out3[1], out3[2], grad, q1)
+
+    def check(self, stream=None) -> int:
+        """Synchronise and report a non-finite loss since the last check."""
+        return _check(lib().lddmm_ctx_check(self._h, _stream(stream)), self._h)
+
+
+def version() -> str:
+    return lib().lddmm_version().decode()
