@@ -111,6 +111,24 @@ lddmm_status lddmm_shoot_grad(lddmm_ctx* ctx, const lddmm_params* params, const 
  * flag is cleared).  Errors: EINVAL, EDEVICE. */
 lddmm_status lddmm_ctx_check(lddmm_ctx* ctx, void* stream);
 
+/* Per-kernel timing, for benchmarks.  While enabled, every launch of the
+ * forward and of the adjoint pair-sum kernel is bracketed by two HIP events
+ * recorded on the call's stream (the stream the kernel runs on); durations
+ * accumulate until read.  Off by default.  Errors: EINVAL. */
+typedef struct {
+  double fwd_ms;           /* summed duration of forward pair-kernel launches */
+  double adj_ms;           /* summed duration of adjoint pair-kernel launches */
+  int64_t fwd_launches;
+  int64_t adj_launches;
+} lddmm_timing;
+
+lddmm_status lddmm_ctx_set_timing(lddmm_ctx* ctx, int enable);
+
+/* Waits for the recorded launches to finish and returns their totals since
+ * the last reset; reset != 0 starts a new accumulation.  Errors: EINVAL,
+ * EDEVICE. */
+lddmm_status lddmm_ctx_timing(lddmm_ctx* ctx, lddmm_timing* out, int reset);
+
 /* Static description of a status code; never NULL. */
 const char* lddmm_status_string(lddmm_status status);
 

@@ -8,17 +8,70 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 using namespace lddmm;
+
+namespace {
+
+// Event pairs bracketing pair-kernel launches (benchmark timing).
+struct Timer {
+  struct Rec { hipEvent_t ev[2]; int kind; };   // kind 0: forward, 1: adjoint
+  bool on = false;
+  std::vector<Rec> pending, spare;
+  double ms[2] = {0.0, 0.0};
+  int64_t count[2] = {0, 0};
+
+  // Events for the next launch of `kind`, or null when timing is off.
+  hipEvent_t* take(int kind) {
+    if (!on) return nullptr;
+    Rec r{};
+    if (!spare.empty()) {
+      r = spare.back();
+      spare.pop_back();
+    } else if (hipEventCreate(&r.ev[0]) != hipSuccess || hipEventCreate(&r.ev[1]) != hipSuccess) {
+      return nullptr;
+    }
+    r.kind = kind;
+    pending.push_back(r);
+    return pending.back().ev;
+  }
+
+  hipError_t collect() {
+    for (Rec& r : pending) {
+      hipError_t e = hipEventSynchronize(r.ev[1]);
+      if (e != hipSuccess) return e;
+      float t = 0.0f;
+      e = hipEventElapsedTime(&t, r.ev[0], r.ev[1]);
+      if (e != hipSuccess) return e;
+      ms[r.kind] += t;
+      count[r.kind] += 1;
+      spare.push_back(r);
+    }
+    pending.clear();
+    return hipSuccess;
+  }
+
+  void destroy() {
+    for (auto* v : {&pending, &spare})
+      for (Rec& r : *v) { (void)hipEventDestroy(r.ev[0]); (void)hipEventDestroy(r.ev[1]); }
+    pending.clear();
+    spare.clear();
+  }
+};
+
+}  // namespace
 
 struct lddmm_ctx {
   int device = 0;
   void* ws = nullptr;        // workspace
   size_t ws_bytes = 0;
   int* flag = nullptr;       // device non-finite flag
+  Timer timer;
   std::string err;
 };
 
@@ -26,8 +79,16 @@ namespace {
 
 thread_local std::string g_err;   // errors that have no context
 
-// Waves the pair kernels aim to keep in flight: 256 CUs x 4 SIMDs x 4.
-constexpr int kTargetWaves = 4096;
+// Waves the pair kernels aim to keep in flight (256 CUs x 4 SIMDs x 4);
+// LDDMM_TARGET_WAVES overrides it for tuning.
+int target_waves() {
+  static const int v = [] {
+    const char* e = std::getenv("LDDMM_TARGET_WAVES");
+    const int t = e ? std::atoi(e) : 0;
+    return t > 0 ? t : 4096;
+  }();
+  return v;
+}
 
 lddmm_status fail(lddmm_ctx* ctx, lddmm_status st, const char* fmt, ...)
     __attribute__((format(printf, 3, 4)));
@@ -145,7 +206,7 @@ struct Job {
 Job make_job(const lddmm_params& p, void* ws) {
   Job j{};
   j.p = p;
-  j.plan = make_plan(p.n, kTargetWaves);
+  j.plan = make_plan(p.n, target_waves());
   j.sc = make_scales(p.sigma, p.T);
   j.L = make_layout(p, j.plan);
   j.ws = ws;
@@ -165,7 +226,8 @@ Job make_job(const lddmm_params& p, void* ws) {
 }
 
 // Forward Euler steps t in [t0, t1).  first: capture Hp(q0,p0) and H0 at t == 0.
-hipError_t run_forward(const Job& j, int t0, int t1, bool first, bool store_ckpt, hipStream_t s) {
+hipError_t run_forward(const Job& j, int t0, int t1, bool first, bool store_ckpt, hipStream_t s,
+                       Timer* tm) {
   const int mode = j.p.precision;
   for (int t = t0; t < t1; ++t) {
     FwdArgs a{};
@@ -180,14 +242,15 @@ hipError_t run_forward(const Job& j, int t0, int t1, bool first, bool store_ckpt
     a.ckpt = (store_ckpt && j.L.nseg > 0 && (t + 1) % s_every == 0 && t + 1 < j.p.T)
                  ? j.ckpt_state((t + 1) / s_every) : nullptr;
     a.partial = j.partial;
-    hipError_t e = launch_fwd_step(mode, j.plan, a, s);
+    hipError_t e = launch_fwd_step(mode, j.plan, a, s, tm->take(0));
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
 // Adjoint steps t = t1-1 down to t0; *cur is the adjoint record buffer in use.
-hipError_t run_adjoint(const Job& j, int t0, int t1, int* cur, double* grad, hipStream_t s) {
+hipError_t run_adjoint(const Job& j, int t0, int t1, int* cur, double* grad, hipStream_t s,
+                       Timer* tm) {
   const int mode = j.p.precision;
   for (int t = t1 - 1; t >= t0; --t) {
     AdjArgs a{};
@@ -200,7 +263,7 @@ hipError_t run_adjoint(const Job& j, int t0, int t1, int* cur, double* grad, hip
     a.hp0 = j.hp0;
     a.grad = t == 0 ? grad : nullptr;
     a.partial = j.partial;
-    hipError_t e = launch_adj_step(mode, j.plan, a, s);
+    hipError_t e = launch_adj_step(mode, j.plan, a, s, tm->take(1));
     if (e != hipSuccess) return e;
     *cur ^= 1;
   }
@@ -211,7 +274,7 @@ lddmm_status begin(lddmm_ctx* ctx, const lddmm_params* params, Job* job) {
   if (!ctx) return fail(nullptr, LDDMM_EINVAL, "ctx is NULL");
   lddmm_status st = check_params(ctx, params);
   if (st != LDDMM_OK) return st;
-  const Plan plan = make_plan(params->n, kTargetWaves);
+  const Plan plan = make_plan(params->n, target_waves());
   const Layout L = make_layout(*params, plan);
   st = ensure_ws(ctx, L.total);
   if (st != LDDMM_OK) return st;
@@ -270,6 +333,7 @@ lddmm_status lddmm_ctx_destroy(lddmm_ctx* ctx) {
   (void)hipDeviceSynchronize();
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->flag) (void)hipFree(ctx->flag);
+  ctx->timer.destroy();
   delete ctx;
   return LDDMM_OK;
 }
@@ -278,7 +342,7 @@ lddmm_status lddmm_workspace_size(const lddmm_params* params, size_t* bytes) {
   lddmm_status st = check_params(nullptr, params);
   if (st != LDDMM_OK) return st;
   if (!bytes) return fail(nullptr, LDDMM_EINVAL, "bytes is NULL");
-  *bytes = make_layout(*params, make_plan(params->n, kTargetWaves)).total;
+  *bytes = make_layout(*params, make_plan(params->n, target_waves())).total;
   return LDDMM_OK;
 }
 
@@ -294,7 +358,7 @@ lddmm_status lddmm_shoot_forward(lddmm_ctx* ctx, const lddmm_params* params, con
   HIP_TRY(ctx, launch_centroid(q0, n, j.cen, s), "centroid");
   HIP_TRY(ctx, launch_stage(params->precision, n, q0, p0, nullptr, j.cen, j.sc.k, j.st, j.xc,
                             j.slot(0), s), "stage");
-  HIP_TRY(ctx, run_forward(j, 0, params->T, true, false, s), "forward step");
+  HIP_TRY(ctx, run_forward(j, 0, params->T, true, false, s, &ctx->timer), "forward step");
   HIP_TRY(ctx, launch_forward_out(n, j.plan.nb, j.st, j.cen, j.h0p, H0, q1, p1, s), "forward out");
   return LDDMM_OK;
 }
@@ -315,13 +379,13 @@ lddmm_status lddmm_shoot_grad(lddmm_ctx* ctx, const lddmm_params* params, const 
   if (j.L.nseg > 0)
     HIP_TRY(ctx, hipMemcpyAsync(j.ckpt_state(0), j.st, 6 * (size_t)n * 8, hipMemcpyDeviceToDevice, s),
             "checkpoint 0");
-  HIP_TRY(ctx, run_forward(j, 0, T, true, true, s), "forward step");
+  HIP_TRY(ctx, run_forward(j, 0, T, true, true, s, &ctx->timer), "forward step");
   HIP_TRY(ctx, launch_loss(mode, n, j.plan.nb, params->lambda, j.sc.bscale, j.st, j.xc, j.cen,
                            j.h0p, j.ad, j.arec_buf(0), out3, q1, nullptr, ctx->flag, s),
           "loss");
   int cur = 0;
   if (j.L.nseg == 0) {
-    HIP_TRY(ctx, run_adjoint(j, 0, T, &cur, grad, s), "adjoint step");
+    HIP_TRY(ctx, run_adjoint(j, 0, T, &cur, grad, s, &ctx->timer), "adjoint step");
   } else {
     const int every = params->ckpt_every;
     for (int seg = j.L.nseg - 1; seg >= 0; --seg) {
@@ -329,10 +393,31 @@ lddmm_status lddmm_shoot_grad(lddmm_ctx* ctx, const lddmm_params* params, const 
       if (seg != j.L.nseg - 1) {   // the last segment is still in the ring of slots
         HIP_TRY(ctx, launch_restore(mode, n, j.ckpt_state(seg), j.sc.k, j.st, j.slot(t0), s),
                 "restore");
-        HIP_TRY(ctx, run_forward(j, t0, t1, false, false, s), "recompute step");
+        HIP_TRY(ctx, run_forward(j, t0, t1, false, false, s, &ctx->timer), "recompute step");
       }
-      HIP_TRY(ctx, run_adjoint(j, t0, t1, &cur, grad, s), "adjoint step");
+      HIP_TRY(ctx, run_adjoint(j, t0, t1, &cur, grad, s, &ctx->timer), "adjoint step");
     }
+  }
+  return LDDMM_OK;
+}
+
+lddmm_status lddmm_ctx_set_timing(lddmm_ctx* ctx, int enable) {
+  if (!ctx) return fail(nullptr, LDDMM_EINVAL, "ctx is NULL");
+  ctx->timer.on = enable != 0;
+  return LDDMM_OK;
+}
+
+lddmm_status lddmm_ctx_timing(lddmm_ctx* ctx, lddmm_timing* out, int reset) {
+  if (!ctx || !out) return fail(ctx, LDDMM_EINVAL, "ctx and out must not be NULL");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  HIP_TRY(ctx, ctx->timer.collect(), "timing events");
+  out->fwd_ms = ctx->timer.ms[0];
+  out->adj_ms = ctx->timer.ms[1];
+  out->fwd_launches = ctx->timer.count[0];
+  out->adj_launches = ctx->timer.count[1];
+  if (reset) {
+    ctx->timer.ms[0] = ctx->timer.ms[1] = 0.0;
+    ctx->timer.count[0] = ctx->timer.count[1] = 0;
   }
   return LDDMM_OK;
 }

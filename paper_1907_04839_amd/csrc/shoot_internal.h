@@ -76,8 +76,11 @@ hipError_t launch_stage(int mode, int n, const double* q0, const double* p0, con
                         hipStream_t s);
 hipError_t launch_restore(int mode, int n, const double* ckpt, double k, double* st, void* rec,
                           hipStream_t s);
-hipError_t launch_fwd_step(int mode, const Plan& p, const FwdArgs& a, hipStream_t s);
-hipError_t launch_adj_step(int mode, const Plan& p, const AdjArgs& a, hipStream_t s);
+// ev (optional): two events recorded on s around the pair kernel alone.
+hipError_t launch_fwd_step(int mode, const Plan& p, const FwdArgs& a, hipStream_t s,
+                           hipEvent_t* ev = nullptr);
+hipError_t launch_adj_step(int mode, const Plan& p, const AdjArgs& a, hipStream_t s,
+                           hipEvent_t* ev = nullptr);
 // Loss and terminal adjoint: L = H0 + lambda |q(1) - x|^2, a = 2 lambda (q(1) - x), b = 0.
 // out3 = {loss, H0, mismatch}; q1/p1 (optional) receive the final state, uncentred, [n][3].
 hipError_t launch_loss(int mode, int n, int nb, double lambda, double bscale, const double* st,

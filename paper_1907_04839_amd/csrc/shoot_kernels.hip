@@ -256,11 +256,10 @@ __global__ __launch_bounds__(64 * W) void k_fwd(FwdArgs A) {
   wave_sums<R, COMP, NC>(j0, j1, o, [&](int a, int b, auto* h) { fwd_range<R>(X, ri, a, b, h); });
   block_combine<Acc, NC, W>(red, o, w, lane);
   if (A.S == 1) {
-    if (w == 0) {
-      double hp[3], hq[3];
-      for (int c = 0; c < 3; ++c) { hp[c] = red[c * 64 + lane]; hq[c] = red[(3 + c) * 64 + lane]; }
-      fwd_finish<R>(A, ib, lane, hp, hq);
-    }
+    if (w != 0) return;
+    double h[NC];
+    for (int c = 0; c < NC; ++c) h[c] = red[c * 64 + lane];
+    fwd_finish<R>(A, ib, lane, h, h + 3);
   } else {
     Acc* P = static_cast<Acc*>(A.partial);
     for (int idx = threadIdx.x; idx < NC * 64; idx += 64 * W) {
@@ -293,11 +292,10 @@ __global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
                          [&](int a, int b, auto* h) { adj_range<R>(X, Y, ri, yi, a, b, h); });
   block_combine<Acc, NC, W>(red, o, w, lane);
   if (A.S == 1) {
-    if (w == 0) {
-      double v[NC];
-      for (int c = 0; c < NC; ++c) v[c] = red[c * 64 + lane];
-      adj_finish<R>(A, ib, lane, v);
-    }
+    if (w != 0) return;
+    double h[NC];
+    for (int c = 0; c < NC; ++c) h[c] = red[c * 64 + lane];
+    adj_finish<R>(A, ib, lane, h);
   } else {
     Acc* P = static_cast<Acc*>(A.partial);
     for (int idx = threadIdx.x; idx < NC * 64; idx += 64 * W) {
@@ -307,7 +305,10 @@ __global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
   }
 }
 
-// Split path: combine the S workgroup partials in chunk order, then update.
+// Split path (S > 1): combine the S workgroup partials in chunk order, then
+// update.  A separate launch: combining through memory inside the pair
+// kernel needs agent-scope release/acquire per workgroup, whose L2
+// write-back and invalidate cost more than this launch.
 template <typename R, bool COMP>
 __global__ __launch_bounds__(64) void k_fwd_update(FwdArgs A) {
   using Acc = typename AccOf<R, COMP>::type;
@@ -454,8 +455,9 @@ __global__ __launch_bounds__(kLossThreads) void k_forward_out(
 // launch helpers
 // ---------------------------------------------------------------------------
 template <typename R, bool COMP>
-hipError_t fwd_dispatch(const Plan& p, const FwdArgs& a, hipStream_t s) {
+hipError_t fwd_dispatch(const Plan& p, const FwdArgs& a, hipStream_t s, hipEvent_t* ev) {
   const dim3 grid(p.nb * p.S);
+  if (ev) (void)hipEventRecord(ev[0], s);
   switch (p.W) {
     case 1: k_fwd<R, COMP, 1><<<grid, 64, 0, s>>>(a); break;
     case 2: k_fwd<R, COMP, 2><<<grid, 128, 0, s>>>(a); break;
@@ -464,13 +466,15 @@ hipError_t fwd_dispatch(const Plan& p, const FwdArgs& a, hipStream_t s) {
     case 16: k_fwd<R, COMP, 16><<<grid, 1024, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
+  if (ev) (void)hipEventRecord(ev[1], s);
   if (p.S > 1) k_fwd_update<R, COMP><<<p.nb, 64, 0, s>>>(a);
   return hipGetLastError();
 }
 
 template <typename R, bool COMP>
-hipError_t adj_dispatch(const Plan& p, const AdjArgs& a, hipStream_t s) {
+hipError_t adj_dispatch(const Plan& p, const AdjArgs& a, hipStream_t s, hipEvent_t* ev) {
   const dim3 grid(p.nb * p.S);
+  if (ev) (void)hipEventRecord(ev[0], s);
   switch (p.W) {
     case 1: k_adj<R, COMP, 1><<<grid, 64, 0, s>>>(a); break;
     case 2: k_adj<R, COMP, 2><<<grid, 128, 0, s>>>(a); break;
@@ -479,6 +483,7 @@ hipError_t adj_dispatch(const Plan& p, const AdjArgs& a, hipStream_t s) {
     case 16: k_adj<R, COMP, 16><<<grid, 1024, 0, s>>>(a); break;
     default: return hipErrorInvalidValue;
   }
+  if (ev) (void)hipEventRecord(ev[1], s);
   if (p.S > 1) k_adj_update<R, COMP><<<p.nb, 64, 0, s>>>(a);
   return hipGetLastError();
 }
@@ -552,20 +557,22 @@ hipError_t launch_restore(int mode, int n, const double* ckpt, double k, double*
   return hipGetLastError();
 }
 
-hipError_t launch_fwd_step(int mode, const Plan& p, const FwdArgs& a, hipStream_t s) {
+hipError_t launch_fwd_step(int mode, const Plan& p, const FwdArgs& a, hipStream_t s,
+                           hipEvent_t* ev) {
   switch (mode) {
-    case kFP32: return fwd_dispatch<float, false>(p, a, s);
-    case kFP32Comp: return fwd_dispatch<float, true>(p, a, s);
-    case kFP64: return fwd_dispatch<double, false>(p, a, s);
+    case kFP32: return fwd_dispatch<float, false>(p, a, s, ev);
+    case kFP32Comp: return fwd_dispatch<float, true>(p, a, s, ev);
+    case kFP64: return fwd_dispatch<double, false>(p, a, s, ev);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_adj_step(int mode, const Plan& p, const AdjArgs& a, hipStream_t s) {
+hipError_t launch_adj_step(int mode, const Plan& p, const AdjArgs& a, hipStream_t s,
+                           hipEvent_t* ev) {
   switch (mode) {
-    case kFP32: return adj_dispatch<float, false>(p, a, s);
-    case kFP32Comp: return adj_dispatch<float, true>(p, a, s);
-    case kFP64: return adj_dispatch<double, false>(p, a, s);
+    case kFP32: return adj_dispatch<float, false>(p, a, s, ev);
+    case kFP32Comp: return adj_dispatch<float, true>(p, a, s, ev);
+    case kFP64: return adj_dispatch<double, false>(p, a, s, ev);
   }
   return hipErrorInvalidValue;
 }

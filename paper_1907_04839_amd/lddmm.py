@@ -31,6 +31,11 @@ class Params(ctypes.Structure):
                 ("ckpt_every", ctypes.c_int32)]
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("fwd_ms", ctypes.c_double), ("adj_ms", ctypes.c_double),
+                ("fwd_launches", ctypes.c_int64), ("adj_launches", ctypes.c_int64)]
+
+
 class LddmmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -54,13 +59,16 @@ def lib():
         L.lddmm_shoot_forward.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp]
         L.lddmm_shoot_grad.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.lddmm_ctx_check.argtypes = [_vp, _vp]
+        L.lddmm_ctx_set_timing.argtypes = [_vp, ctypes.c_int]
+        L.lddmm_ctx_timing.argtypes = [_vp, ctypes.POINTER(Timing), ctypes.c_int]
         L.lddmm_status_string.argtypes = [ctypes.c_int]
         L.lddmm_status_string.restype = ctypes.c_char_p
         L.lddmm_last_error.argtypes = [_vp]
         L.lddmm_last_error.restype = ctypes.c_char_p
         L.lddmm_version.restype = ctypes.c_char_p
         for f in ("lddmm_ctx_create", "lddmm_ctx_destroy", "lddmm_workspace_size",
-                  "lddmm_shoot_forward", "lddmm_shoot_grad", "lddmm_ctx_check"):
+                  "lddmm_shoot_forward", "lddmm_shoot_grad", "lddmm_ctx_check",
+                  "lddmm_ctx_set_timing", "lddmm_ctx_timing"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -177,6 +185,17 @@ class Context:
                                       q1.data_ptr() if q1 is not None else None,
                                       _stream(stream)), self._h)
         return GradResult(out3[0], out3[1], out3[2], grad, q1)
+
+    def set_timing(self, enable: bool) -> None:
+        """Bracket every pair-kernel launch with HIP events on its stream."""
+        _check(lib().lddmm_ctx_set_timing(self._h, int(bool(enable))), self._h)
+
+    def timing(self, reset: bool = True) -> dict:
+        """Summed pair-kernel durations (ms) and launch counts since the last reset."""
+        t = Timing()
+        _check(lib().lddmm_ctx_timing(self._h, ctypes.byref(t), int(bool(reset))), self._h)
+        return dict(fwd_ms=t.fwd_ms, adj_ms=t.adj_ms, fwd_launches=int(t.fwd_launches),
+                    adj_launches=int(t.adj_launches))
 
     def check(self, stream=None) -> int:
         """Synchronise and report a non-finite loss since the last check."""
