@@ -184,29 +184,51 @@ __device__ __forceinline__ void block_combine(Acc* red, const Acc o[NC], int w, 
 // ---------------------------------------------------------------------------
 // per-landmark Euler updates (FP64), shared by the fused and the split path
 // ---------------------------------------------------------------------------
+// FP64 state of one landmark, loaded before the sums it is combined with so
+// that its memory latency overlaps them.
+struct FwdState { double q[3], p[3]; };
+struct AdjState { double a[3], b[3], hp0[3]; };
+
+__device__ __forceinline__ FwdState load_fwd_state(const FwdArgs& A, int i) {
+  FwdState v;
+  const int ic = min(i, A.n - 1);
+  for (int c = 0; c < 3; ++c) { v.q[c] = A.st[c * A.n + ic]; v.p[c] = A.st[(3 + c) * A.n + ic]; }
+  return v;
+}
+
+__device__ __forceinline__ AdjState load_adj_state(const AdjArgs& A, int i) {
+  AdjState v;
+  const int ic = min(i, A.n - 1);
+  for (int c = 0; c < 3; ++c) {
+    v.a[c] = A.ad[c * A.n + ic];
+    v.b[c] = A.ad[(3 + c) * A.n + ic];
+    v.hp0[c] = A.grad ? A.hp0[c * A.n + ic] : 0.0;
+  }
+  return v;
+}
+
 template <typename R>
-__device__ __forceinline__ void fwd_finish(const FwdArgs& A, int ib, int lane, const double hp[3],
-                                           const double hqs[3]) {
+__device__ __forceinline__ void fwd_finish(const FwdArgs& A, int ib, int lane, FwdState v,
+                                           const double hp[3], const double hqs[3]) {
   const int n = A.n;
   const int i = ib * 64 + lane;
   double h0 = 0.0;
   if (i < n) {
-    double q[3], p[3];
-    for (int c = 0; c < 3; ++c) { q[c] = A.st[c * n + i]; p[c] = A.st[(3 + c) * n + i]; }
     if (A.hp0) {
       for (int c = 0; c < 3; ++c) A.hp0[c * n + i] = hp[c];
-      h0 = p[0] * hp[0] + p[1] * hp[1] + p[2] * hp[2];
+      h0 = v.p[0] * hp[0] + v.p[1] * hp[1] + v.p[2] * hp[2];
     }
     for (int c = 0; c < 3; ++c) {
       const double hq = A.sc.hq * hqs[c];
-      q[c] = q[c] + A.sc.dt * hp[c];
-      p[c] = p[c] - A.sc.dt * hq;
+      v.q[c] = v.q[c] + A.sc.dt * hp[c];
+      v.p[c] = v.p[c] - A.sc.dt * hq;
     }
-    for (int c = 0; c < 3; ++c) { A.st[c * n + i] = q[c]; A.st[(3 + c) * n + i] = p[c]; }
+    for (int c = 0; c < 3; ++c) { A.st[c * n + i] = v.q[c]; A.st[(3 + c) * n + i] = v.p[c]; }
     if (A.ckpt)
-      for (int c = 0; c < 3; ++c) { A.ckpt[c * n + i] = q[c]; A.ckpt[(3 + c) * n + i] = p[c]; }
+      for (int c = 0; c < 3; ++c) { A.ckpt[c * n + i] = v.q[c]; A.ckpt[(3 + c) * n + i] = v.p[c]; }
     const double k = A.sc.k;
-    static_cast<Rec<R>*>(A.rec_t1)[i] = make_rec<R>(k * q[0], k * q[1], k * q[2], p[0], p[1], p[2]);
+    static_cast<Rec<R>*>(A.rec_t1)[i] =
+        make_rec<R>(k * v.q[0], k * v.q[1], k * v.q[2], v.p[0], v.p[1], v.p[2]);
   }
   if (A.h0_part) {          // whole wave takes part: fixed butterfly order
     for (int off = 32; off > 0; off >>= 1) h0 += __shfl_xor(h0, off, 64);
@@ -215,23 +237,23 @@ __device__ __forceinline__ void fwd_finish(const FwdArgs& A, int ib, int lane, c
 }
 
 template <typename R>
-__device__ __forceinline__ void adj_finish(const AdjArgs& A, int ib, int lane, const double s[9]) {
+__device__ __forceinline__ void adj_finish(const AdjArgs& A, int ib, int lane, AdjState v,
+                                           const double s[9]) {
   const int n = A.n;
   const int i = ib * 64 + lane;
   if (i >= n) return;
-  double a[3], b[3];
-  for (int c = 0; c < 3; ++c) { a[c] = A.ad[c * n + i]; b[c] = A.ad[(3 + c) * n + i]; }
   const double inv_kappa = 1.0 / A.sc.kappa;
   for (int c = 0; c < 3; ++c) {
     const double Ac = A.sc.adj_a * (s[c] * inv_kappa - s[3 + c]);
-    a[c] = a[c] + A.sc.dt * Ac;
-    b[c] = b[c] + A.sc.dt * s[6 + c];
+    v.a[c] = v.a[c] + A.sc.dt * Ac;
+    v.b[c] = v.b[c] + A.sc.dt * s[6 + c];
   }
-  for (int c = 0; c < 3; ++c) { A.ad[c * n + i] = a[c]; A.ad[(3 + c) * n + i] = b[c]; }
+  for (int c = 0; c < 3; ++c) { A.ad[c * n + i] = v.a[c]; A.ad[(3 + c) * n + i] = v.b[c]; }
   const double bs = A.sc.bscale;
-  static_cast<Rec<R>*>(A.arec_next)[i] = make_rec<R>(a[0], a[1], a[2], bs * b[0], bs * b[1], bs * b[2]);
+  static_cast<Rec<R>*>(A.arec_next)[i] =
+      make_rec<R>(v.a[0], v.a[1], v.a[2], bs * v.b[0], bs * v.b[1], bs * v.b[2]);
   if (A.grad)
-    for (int c = 0; c < 3; ++c) A.grad[3 * i + c] = b[c] + A.hp0[c * n + i];
+    for (int c = 0; c < 3; ++c) A.grad[3 * i + c] = v.b[c] + v.hp0[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -252,6 +274,8 @@ __global__ __launch_bounds__(64 * W) void k_fwd(FwdArgs A) {
   const int je = min(A.n, jb + A.chunk);
   const int j0 = min(je, jb + w * A.wchunk);
   const int j1 = min(je, j0 + A.wchunk);
+  FwdState v{};
+  if (A.S == 1 && w == 0) v = load_fwd_state(A, ib * 64 + lane);
   Acc o[NC];
   wave_sums<R, COMP, NC>(j0, j1, o, [&](int a, int b, auto* h) { fwd_range<R>(X, ri, a, b, h); });
   block_combine<Acc, NC, W>(red, o, w, lane);
@@ -259,7 +283,7 @@ __global__ __launch_bounds__(64 * W) void k_fwd(FwdArgs A) {
     if (w != 0) return;
     double h[NC];
     for (int c = 0; c < NC; ++c) h[c] = red[c * 64 + lane];
-    fwd_finish<R>(A, ib, lane, h, h + 3);
+    fwd_finish<R>(A, ib, lane, v, h, h + 3);
   } else {
     Acc* P = static_cast<Acc*>(A.partial);
     for (int idx = threadIdx.x; idx < NC * 64; idx += 64 * W) {
@@ -287,6 +311,8 @@ __global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
   const int je = min(A.n, jb + A.chunk);
   const int j0 = min(je, jb + w * A.wchunk);
   const int j1 = min(je, j0 + A.wchunk);
+  AdjState v{};
+  if (A.S == 1 && w == 0) v = load_adj_state(A, ib * 64 + lane);
   Acc o[NC];
   wave_sums<R, COMP, NC>(j0, j1, o,
                          [&](int a, int b, auto* h) { adj_range<R>(X, Y, ri, yi, a, b, h); });
@@ -295,7 +321,7 @@ __global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
     if (w != 0) return;
     double h[NC];
     for (int c = 0; c < NC; ++c) h[c] = red[c * 64 + lane];
-    adj_finish<R>(A, ib, lane, h);
+    adj_finish<R>(A, ib, lane, v, h);
   } else {
     Acc* P = static_cast<Acc*>(A.partial);
     for (int idx = threadIdx.x; idx < NC * 64; idx += 64 * W) {
@@ -308,35 +334,59 @@ __global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
 // Split path (S > 1): combine the S workgroup partials in chunk order, then
 // update.  A separate launch: combining through memory inside the pair
 // kernel needs agent-scope release/acquire per workgroup, whose L2
-// write-back and invalidate cost more than this launch.
-template <typename R, bool COMP>
-__global__ __launch_bounds__(64) void k_fwd_update(FwdArgs A) {
-  using Acc = typename AccOf<R, COMP>::type;
-  const int ib = blockIdx.x, lane = threadIdx.x;
-  const int ic = min(ib * 64 + lane, A.n - 1);
-  const Acc* P = static_cast<const Acc*>(A.partial);
-  double h[6];
-  for (int c = 0; c < 6; ++c) {
-    Acc sum = P[(size_t)c * A.n + ic];
-    for (int s = 1; s < A.S; ++s) sum += P[((size_t)s * 6 + c) * A.n + ic];
-    h[c] = sum;
+// write-back and invalidate cost more than this launch.  The partials were
+// written by workgroups on other XCDs, so every load is a memory round
+// trip: with the chunk count SC known at compile time all of them are in
+// flight at once (SC = 0: any S, loaded chunk by chunk).
+template <typename Acc, int NC, int SC>
+__device__ __forceinline__ void gather_partials(const Acc* __restrict__ P, int n, int S, int ic,
+                                                double h[NC]) {
+  if constexpr (SC > 0) {
+    Acc v[SC][NC];
+#pragma unroll
+    for (int s = 0; s < SC; ++s)
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[s][c] = P[((size_t)s * NC + c) * n + ic];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      Acc sum = v[0][c];
+#pragma unroll
+      for (int s = 1; s < SC; ++s) sum += v[s][c];
+      h[c] = sum;
+    }
+  } else {
+    Acc sum[NC];
+    for (int c = 0; c < NC; ++c) sum[c] = P[(size_t)c * n + ic];
+    for (int s = 1; s < S; ++s)
+      for (int c = 0; c < NC; ++c) sum[c] += P[((size_t)s * NC + c) * n + ic];
+    for (int c = 0; c < NC; ++c) h[c] = sum[c];
   }
-  fwd_finish<R>(A, ib, lane, h, h + 3);
 }
 
-template <typename R, bool COMP>
-__global__ __launch_bounds__(64) void k_adj_update(AdjArgs A) {
+// One wave per i-block and latency-bound: let the scheduler spend registers
+// on loads in flight rather than on occupancy.
+#define LDDMM_LATENCY_BOUND __attribute__((amdgpu_waves_per_eu(1, 2)))
+
+template <typename R, bool COMP, int SC>
+__global__ __launch_bounds__(64) LDDMM_LATENCY_BOUND void k_fwd_update(FwdArgs A) {
   using Acc = typename AccOf<R, COMP>::type;
   const int ib = blockIdx.x, lane = threadIdx.x;
-  const int ic = min(ib * 64 + lane, A.n - 1);
-  const Acc* P = static_cast<const Acc*>(A.partial);
+  const FwdState v = load_fwd_state(A, ib * 64 + lane);
+  double h[6];
+  gather_partials<Acc, 6, SC>(static_cast<const Acc*>(A.partial), A.n, A.S,
+                              min(ib * 64 + lane, A.n - 1), h);
+  fwd_finish<R>(A, ib, lane, v, h, h + 3);
+}
+
+template <typename R, bool COMP, int SC>
+__global__ __launch_bounds__(64) LDDMM_LATENCY_BOUND void k_adj_update(AdjArgs A) {
+  using Acc = typename AccOf<R, COMP>::type;
+  const int ib = blockIdx.x, lane = threadIdx.x;
+  const AdjState v = load_adj_state(A, ib * 64 + lane);
   double h[9];
-  for (int c = 0; c < 9; ++c) {
-    Acc sum = P[(size_t)c * A.n + ic];
-    for (int s = 1; s < A.S; ++s) sum += P[((size_t)s * 9 + c) * A.n + ic];
-    h[c] = sum;
-  }
-  adj_finish<R>(A, ib, lane, h);
+  gather_partials<Acc, 9, SC>(static_cast<const Acc*>(A.partial), A.n, A.S,
+                              min(ib * 64 + lane, A.n - 1), h);
+  adj_finish<R>(A, ib, lane, v, h);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,7 +517,14 @@ hipError_t fwd_dispatch(const Plan& p, const FwdArgs& a, hipStream_t s, hipEvent
     default: return hipErrorInvalidValue;
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (p.S > 1) k_fwd_update<R, COMP><<<p.nb, 64, 0, s>>>(a);
+  switch (p.S) {
+    case 1: break;
+    case 2: k_fwd_update<R, COMP, 2><<<p.nb, 64, 0, s>>>(a); break;
+    case 3: k_fwd_update<R, COMP, 3><<<p.nb, 64, 0, s>>>(a); break;
+    case 4: k_fwd_update<R, COMP, 4><<<p.nb, 64, 0, s>>>(a); break;
+    case 8: k_fwd_update<R, COMP, 8><<<p.nb, 64, 0, s>>>(a); break;
+    default: k_fwd_update<R, COMP, 0><<<p.nb, 64, 0, s>>>(a); break;
+  }
   return hipGetLastError();
 }
 
@@ -484,7 +541,14 @@ hipError_t adj_dispatch(const Plan& p, const AdjArgs& a, hipStream_t s, hipEvent
     default: return hipErrorInvalidValue;
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (p.S > 1) k_adj_update<R, COMP><<<p.nb, 64, 0, s>>>(a);
+  switch (p.S) {
+    case 1: break;
+    case 2: k_adj_update<R, COMP, 2><<<p.nb, 64, 0, s>>>(a); break;
+    case 3: k_adj_update<R, COMP, 3><<<p.nb, 64, 0, s>>>(a); break;
+    case 4: k_adj_update<R, COMP, 4><<<p.nb, 64, 0, s>>>(a); break;
+    case 8: k_adj_update<R, COMP, 8><<<p.nb, 64, 0, s>>>(a); break;
+    default: k_adj_update<R, COMP, 0><<<p.nb, 64, 0, s>>>(a); break;
+  }
   return hipGetLastError();
 }
 
