@@ -106,6 +106,53 @@ lddmm_status lddmm_shoot_grad(lddmm_ctx* ctx, const lddmm_params* params, const 
                               const double* p0, const double* target, double* out3,
                               double* grad, double* q1, void* stream);
 
+/* Options of lddmm_solve (L-BFGS over p0 with a strong-Wolfe line search;
+ * Nocedal & Wright, Numerical Optimization, Algs. 3.5, 3.6 and 7.4). */
+typedef struct {
+  int32_t max_iter;        /* accepted steps (the paper's I), >= 0 */
+  int32_t m;               /* curvature pairs kept, 1..16 */
+  int32_t max_fev;         /* evaluations per line search, >= 1 */
+  double gtol;             /* converged when |g| <= gtol max(1, |p0|) */
+  double ftol_rel;         /* converged when the relative decrease of L is below
+                              this (0 disables the test) */
+  double c1, c2;           /* Wolfe constants, 0 < c1 < c2 < 1 */
+  int32_t init;            /* start: 0 p0 = 0; 1 p0 = (target - q0)/T (Alg. 1);
+                              2 the caller's p0 */
+} lddmm_solve_opts;
+
+typedef struct {
+  double loss;             /* L at the returned p0 */
+  double H0;               /* H(q0, p0) */
+  double mismatch;         /* sum_i |q_i(1) - x_i|^2 */
+  double grad_norm;        /* |dL/dp0| at the returned p0 */
+  double avg_dist;         /* mean_i |q_i(1) - x_i| (Sec. 3.1 AverageDist) */
+  double max_dist;         /* max_i |q_i(1) - x_i|  (Sec. 3.1 MaxDist) */
+  int32_t iters;           /* accepted L-BFGS steps */
+  int32_t fevals;          /* loss+gradient evaluations, line-search trials included */
+  int32_t status;          /* lddmm_status of the solve */
+} lddmm_solve_result;
+
+/* Default options: max_iter 100, m 5, max_fev 20, gtol 1e-8 for FP64 pair
+ * sums and 1e-6 for FP32, ftol_rel 0, c1 1e-4, c2 0.9, init 0.
+ * Errors: EINVAL. */
+lddmm_status lddmm_solve_opts_default(int32_t precision, lddmm_solve_opts* opts);
+
+/* Registration by geodesic shooting (Alg. 1): minimises the loss of eq. 3
+ * over p0 with L-BFGS that runs on the GPU (every loss+gradient evaluation,
+ * line-search decision and two-loop recursion is device work; the host only
+ * launches evaluations and polls a completion flag).  Blocks until done.
+ *   q0, target : in,  [n][3] device FP64
+ *   p0_inout   : in (opts->init == 2) / out, [n][3] device FP64, the solution
+ *   result     : out, host struct, may be NULL
+ *   trace      : out, host array of 2 (opts->max_iter + 1) doubles, may be
+ *                NULL: (L, |g|) at the start and after each accepted step
+ * Returns LDDMM_OK (converged), LDDMM_ENOTCONV (iteration cap or failed
+ * line search; p0 is the last accepted iterate), LDDMM_ENONFINITE, or an
+ * error (EINVAL, ENOMEM, EDEVICE). */
+lddmm_status lddmm_solve(lddmm_ctx* ctx, const lddmm_params* params, const lddmm_solve_opts* opts,
+                         const double* q0, const double* target, double* p0_inout,
+                         lddmm_solve_result* result, double* trace, void* stream);
+
 /* Waits for the context's work on `stream` and reports whether any call
  * since the last check produced a non-finite loss (then ENONFINITE, and the
  * flag is cleared).  Errors: EINVAL, EDEVICE. */

@@ -1,0 +1,353 @@
+// On-device FP64 L-BFGS over the initial momentum p0 (paper Sec. 2.1 and
+// Alg. 1, steps (e)-(f): line-search evaluations and quasi-Newton updates
+// repeated until convergence or an iteration cap).
+//
+// The paper runs VNL's L-BFGS on the host and pays one host/device round
+// trip per evaluation.  Here the optimiser lives on the GPU: after every
+// loss+gradient evaluation one workgroup advances a line-search state
+// machine and, on acceptance, updates the curvature history and computes the
+// next direction by the two-loop recursion.  The host only launches
+// evaluations and polls a done flag; there is no synchronisation inside an
+// iteration.
+//
+// Algorithm (Nocedal & Wright, Numerical Optimization, Algs. 3.5, 3.6, 7.4):
+//  * direction d = -H g by the two-loop recursion over the m newest pairs
+//    (s, y), scaled by gamma = s.y / y.y of the newest pair; steepest descent
+//    (and a cleared history) when d is not a descent direction;
+//  * first trial step 1/|d| with an empty history, else 1;
+//  * strong-Wolfe search, c1 = 1e-4, c2 = 0.9: steps double until the
+//    bracket closes, then a zoom with the safeguarded cubic minimiser
+//    (midpoint when the cubic is unusable), at most max_fev evaluations;
+//  * a pair is stored only when s.y > 0 and s.y > 1e-16 y.y;
+//  * stop: |g| <= gtol max(1, |x|) (converged), relative decrease below
+//    ftol_rel (converged), max_iter accepted steps, or a failed line search
+//    (not converged; x stays the last accepted point).
+// Every dot product is a fixed-order tree over one workgroup, so the state
+// machine takes the same decisions on every run.
+#include "lbfgs_internal.h"
+
+#include <cmath>
+
+namespace lddmm {
+
+namespace {
+
+constexpr int kThreads = 1024;
+
+enum Phase : int { kInit = 0, kBracket = 1, kZoom = 2 };
+
+__device__ __forceinline__ double block_dot(const double* __restrict__ a,
+                                            const double* __restrict__ b, int m, double* red) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < m; k += kThreads) s += a[k] * b[k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// x_t = x + a d without FMA contraction (the same rounding as x + a*d on a host)
+__device__ __forceinline__ void trial_point(const LbfgsBufs& B, double a) {
+  for (int k = threadIdx.x; k < B.m3; k += kThreads)
+    B.xt[k] = __dadd_rn(B.x[k], __dmul_rn(a, B.d[k]));
+}
+
+// Safeguarded cubic step between (a0,f0,d0) and (a1,f1,d1).
+__device__ double cubic_step(double a0, double f0, double d0, double a1, double f1, double d1) {
+  const double lo = a0 < a1 ? a0 : a1, hi = a0 < a1 ? a1 : a0, w = hi - lo;
+  const double mid = 0.5 * (a0 + a1);
+  const double t1 = d0 + d1 - 3.0 * (f0 - f1) / (a0 - a1);
+  const double disc = t1 * t1 - d0 * d1;
+  if (!(disc >= 0.0)) return mid;
+  double t2 = sqrt(disc);
+  if (a1 < a0) t2 = -t2;
+  const double den = d1 - d0 + 2.0 * t2;
+  const double a = a1 - (a1 - a0) * ((d1 + t2 - t1) / den);
+  if (!isfinite(a) || a < lo + 0.1 * w || a > hi - 0.1 * w) return mid;
+  return a;
+}
+
+// New search direction from g and the history; sets d0, the first trial step
+// and x_t.  Called by every thread; st is the workgroup's shared copy of the
+// state, read by all threads and written by thread 0 only, between barriers.
+__device__ void new_direction(const LbfgsBufs& B, const LbfgsOpts& o, LbfgsState& st,
+                              double* red) {
+  const int m3 = B.m3, M = o.m;
+  const int used = st.used, newest = st.newest;
+  for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] = B.g[k];
+  __syncthreads();
+  for (int h = 0; h < used; ++h) {             // newest to oldest
+    const int s = (newest - h + M) % M;
+    const double* Ss = B.S + (size_t)s * m3;
+    const double* Ys = B.Y + (size_t)s * m3;
+    const double al = st.rho[s] * block_dot(Ss, B.d, m3, red);
+    if (threadIdx.x == 0) st.alpha[s] = al;
+    for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] -= al * Ys[k];
+    __syncthreads();
+  }
+  if (used > 0) {
+    const double* Sn = B.S + (size_t)newest * m3;
+    const double* Yn = B.Y + (size_t)newest * m3;
+    const double gamma = block_dot(Sn, Yn, m3, red) / block_dot(Yn, Yn, m3, red);
+    for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] *= gamma;
+    __syncthreads();
+  }
+  for (int h = used - 1; h >= 0; --h) {         // oldest to newest
+    const int s = (newest - h + M) % M;
+    const double* Ss = B.S + (size_t)s * m3;
+    const double* Ys = B.Y + (size_t)s * m3;
+    const double beta = st.rho[s] * block_dot(Ys, B.d, m3, red);
+    const double al = st.alpha[s];
+    for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] += (al - beta) * Ss[k];
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] = -B.d[k];
+  __syncthreads();
+  double gd = block_dot(B.g, B.d, m3, red);
+  const bool restart = !(gd < 0.0);             // not a descent direction: restart
+  if (restart) {
+    for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] = -B.g[k];
+    __syncthreads();
+    gd = block_dot(B.g, B.d, m3, red);
+  }
+  const double a0 =
+      (restart || used == 0) ? 1.0 / sqrt(block_dot(B.d, B.d, m3, red)) : 1.0;
+  if (threadIdx.x == 0) {
+    if (restart) { st.used = 0; st.newest = -1; }
+    st.d0 = gd;
+    st.a = a0;
+    st.phase = kBracket;
+    st.fev = 0;
+    st.bi = 1;
+    st.a_prev = 0.0;
+    st.f_prev = st.f;
+    st.dp_prev = gd;
+  }
+  trial_point(B, a0);
+  __syncthreads();
+}
+
+// Accepted step: curvature pair, move to x_t, convergence tests, next direction.
+__device__ void accept(const LbfgsBufs& B, const LbfgsOpts& o, LbfgsState& st, double ft,
+                       double* red) {
+  const int m3 = B.m3, M = o.m;
+  const int slot = (st.newest + 1) % M;
+  const double f_old = st.f;
+  double* Ss = B.S + (size_t)slot * m3;
+  double* Ys = B.Y + (size_t)slot * m3;
+  for (int k = threadIdx.x; k < m3; k += kThreads) {
+    Ss[k] = B.xt[k] - B.x[k];
+    Ys[k] = B.gt[k] - B.g[k];
+  }
+  __syncthreads();
+  const double sy = block_dot(Ss, Ys, m3, red);
+  const double yy = block_dot(Ys, Ys, m3, red);
+  for (int k = threadIdx.x; k < m3; k += kThreads) {
+    B.x[k] = B.xt[k];
+    B.g[k] = B.gt[k];
+  }
+  __syncthreads();
+  const double gnorm = sqrt(block_dot(B.g, B.g, m3, red));
+  const double xnorm = sqrt(block_dot(B.x, B.x, m3, red));
+  if (threadIdx.x == 0) {
+    if (sy > 1e-16 * yy && sy > 0.0) {
+      st.rho[slot] = 1.0 / sy;
+      st.newest = slot;
+      if (st.used < M) ++st.used;
+    }
+    st.f = ft;
+    st.iters += 1;
+    st.gnorm = gnorm;
+    if (B.trace && st.iters <= o.max_iter) {
+      B.trace[2 * st.iters] = st.f;
+      B.trace[2 * st.iters + 1] = st.gnorm;
+    }
+    if (gnorm <= o.gtol * fmax(1.0, xnorm)) {
+      st.done = 1; st.status = kConverged;
+    } else if (o.ftol_rel > 0.0 &&
+               f_old - ft <= o.ftol_rel * fmax(fmax(fabs(f_old), fabs(ft)), 1.0)) {
+      st.done = 1; st.status = kConverged;
+    } else if (st.iters >= o.max_iter) {
+      st.done = 1; st.status = kNotConverged;
+    }
+  }
+  __syncthreads();
+  if (!st.done) new_direction(B, o, st, red);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kThreads) void k_lbfgs_init(LbfgsBufs B, LbfgsState* state,
+                                                         int init, const double* __restrict__ q0,
+                                                         const double* __restrict__ x,
+                                                         const double* __restrict__ p_in,
+                                                         double inv_T) {
+  for (int k = threadIdx.x; k < B.m3; k += kThreads) {
+    double v = 0.0;
+    if (init == 1) v = (x[k] - q0[k]) * inv_T;
+    else if (init == 2) v = p_in[k];
+    B.x[k] = v;
+    B.xt[k] = v;
+  }
+  if (threadIdx.x == 0) {
+    LbfgsState s{};
+    s.phase = kInit;
+    s.newest = -1;
+    s.status = kNotConverged;
+    *state = s;
+  }
+}
+
+// Consumes the evaluation at x_t (loss *B.ft, gradient B.gt) and prepares the
+// next trial point, or sets done.
+__global__ __launch_bounds__(kThreads) void k_lbfgs_step(LbfgsBufs B, LbfgsState* state,
+                                                         LbfgsOpts o) {
+  __shared__ double red[kThreads];
+  __shared__ LbfgsState st;
+  __shared__ int action;      // 0 accept, 1 new trial at st.a, 2 failed search
+  if (threadIdx.x == 0) st = *state;
+  __syncthreads();
+  if (st.done) return;
+  const double ft = *B.ft;
+  const int m3 = B.m3;
+  if (threadIdx.x == 0) st.fevals += 1;
+
+  if (st.phase == kInit) {
+    for (int k = threadIdx.x; k < m3; k += kThreads) B.g[k] = B.gt[k];
+    __syncthreads();
+    const double gg = block_dot(B.g, B.g, m3, red);
+    const double xx = block_dot(B.x, B.x, m3, red);
+    if (threadIdx.x == 0) {
+      st.f = ft;
+      st.gnorm = sqrt(gg);
+      if (B.trace) { B.trace[0] = st.f; B.trace[1] = st.gnorm; }
+      if (!isfinite(st.f) || !isfinite(st.gnorm)) { st.done = 1; st.status = kNonFinite; }
+      else if (st.gnorm <= o.gtol * fmax(1.0, sqrt(xx))) { st.done = 1; st.status = kConverged; }
+      else if (o.max_iter <= 0) { st.done = 1; st.status = kNotConverged; }
+    }
+    __syncthreads();
+    if (!st.done) new_direction(B, o, st, red);
+  } else {
+    const double da = block_dot(B.gt, B.d, m3, red);
+    if (threadIdx.x == 0) {
+      const double a = st.a, f = st.f, d0 = st.d0;
+      st.fev += 1;
+      bool to_zoom = false;
+      action = 1;
+      if (st.phase == kBracket) {
+        if (!isfinite(ft) || !isfinite(da) || ft > f + o.c1 * a * d0 ||
+            (st.bi > 1 && ft >= st.f_prev)) {
+          st.a_lo = st.a_prev; st.f_lo = st.f_prev; st.dp_lo = st.dp_prev;
+          st.a_hi = a; st.f_hi = ft; st.dp_hi = da;
+          to_zoom = true;
+        } else if (fabs(da) <= -o.c2 * d0) {
+          action = 0;
+        } else if (da >= 0.0) {
+          st.a_lo = a; st.f_lo = ft; st.dp_lo = da;
+          st.a_hi = st.a_prev; st.f_hi = st.f_prev; st.dp_hi = st.dp_prev;
+          to_zoom = true;
+        } else {
+          st.a_prev = a; st.f_prev = ft; st.dp_prev = da;
+          st.a = 2.0 * a;
+          st.bi += 1;
+          if (st.fev >= o.max_fev) action = 2;
+        }
+      } else {   // zoom: the trial was a_j = st.a
+        if (!isfinite(ft) || !isfinite(da) || ft > f + o.c1 * a * d0 || ft >= st.f_lo) {
+          st.a_hi = a; st.f_hi = ft; st.dp_hi = da;
+        } else if (fabs(da) <= -o.c2 * d0) {
+          action = 0;
+        } else {
+          if (da * (st.a_hi - st.a_lo) >= 0.0) {
+            st.a_hi = st.a_lo; st.f_hi = st.f_lo; st.dp_hi = st.dp_lo;
+          }
+          st.a_lo = a; st.f_lo = ft; st.dp_lo = da;
+        }
+        if (action == 1) to_zoom = true;
+      }
+      if (to_zoom) {
+        st.phase = kZoom;
+        if (st.fev >= o.max_fev ||
+            fabs(st.a_hi - st.a_lo) <= 1e-14 * fabs(st.a_lo) + 1e-300) {
+          action = 2;
+        } else {
+          st.a = (isfinite(st.f_hi) && isfinite(st.dp_hi))
+                     ? cubic_step(st.a_lo, st.f_lo, st.dp_lo, st.a_hi, st.f_hi, st.dp_hi)
+                     : 0.5 * (st.a_lo + st.a_hi);
+        }
+      }
+      if (action == 2) { st.done = 1; st.status = kNotConverged; }
+    }
+    __syncthreads();
+    if (action == 0) accept(B, o, st, ft, red);
+    else if (action == 1) trial_point(B, st.a);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *state = st;
+}
+
+// Result of a finished solve: AverageDist / MaxDist of q(1) against x
+// (Sec. 3.1) from the final evaluation, and the solver's counters.
+__global__ __launch_bounds__(kThreads) void k_lbfgs_result(int n, const double* __restrict__ q1,
+                                                           const double* __restrict__ x,
+                                                           const double* __restrict__ out3,
+                                                           const LbfgsState* __restrict__ state,
+                                                           LbfgsResult* __restrict__ res) {
+  __shared__ double red[kThreads];
+  __shared__ double redm[kThreads];
+  double s = 0.0, mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += kThreads) {
+    const double dx = q1[3 * i] - x[3 * i], dy = q1[3 * i + 1] - x[3 * i + 1],
+                 dz = q1[3 * i + 2] - x[3 * i + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    s += r;
+    mx = fmax(mx, r);
+  }
+  red[threadIdx.x] = s;
+  redm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      red[threadIdx.x] += red[threadIdx.x + off];
+      redm[threadIdx.x] = fmax(redm[threadIdx.x], redm[threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    res->loss = out3[0];
+    res->H0 = out3[1];
+    res->mismatch = out3[2];
+    res->grad_norm = state->gnorm;
+    res->avg_dist = red[0] / n;
+    res->max_dist = redm[0];
+    res->iters = state->iters;
+    res->fevals = state->fevals;
+    res->status = state->status;
+    res->done = state->done;
+  }
+}
+
+hipError_t launch_lbfgs_init(const LbfgsBufs& B, LbfgsState* state, int init, const double* q0,
+                             const double* x, const double* p_in, int T, hipStream_t s) {
+  k_lbfgs_init<<<1, kThreads, 0, s>>>(B, state, init, q0, x, p_in, 1.0 / T);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_step(const LbfgsBufs& B, LbfgsState* state, const LbfgsOpts& o,
+                             hipStream_t s) {
+  k_lbfgs_step<<<1, kThreads, 0, s>>>(B, state, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_result(int n, const double* q1, const double* x, const double* out3,
+                               const LbfgsState* state, LbfgsResult* res, hipStream_t s) {
+  k_lbfgs_result<<<1, kThreads, 0, s>>>(n, q1, x, out3, state, res);
+  return hipGetLastError();
+}
+
+}  // namespace lddmm

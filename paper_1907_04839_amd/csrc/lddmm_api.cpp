@@ -2,6 +2,7 @@
 // order of kernel launches for one forward pass, the loss, and one adjoint
 // pass (Alg. 1, ComputeGradient), optionally with checkpoint recompute.
 #include "lddmm.h"
+#include "lbfgs_internal.h"
 #include "shoot_internal.h"
 
 #include <algorithm>
@@ -72,6 +73,10 @@ struct lddmm_ctx {
   size_t ws_bytes = 0;
   int* flag = nullptr;       // device non-finite flag
   Timer timer;
+  void* sws = nullptr;       // solver workspace
+  size_t sws_bytes = 0;
+  int* host_done = nullptr;  // pinned: two done flags of the solver poll
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   std::string err;
 };
 
@@ -283,6 +288,40 @@ lddmm_status begin(lddmm_ctx* ctx, const lddmm_params* params, Job* job) {
   return LDDMM_OK;
 }
 
+// One loss+gradient evaluation (Alg. 1 ComputeGradient) of a prepared job.
+lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const double* p0,
+                      const double* target, double* out3, double* grad, double* q1,
+                      hipStream_t s) {
+  const lddmm_params* params = &j.p;
+  const int n = params->n, T = params->T, mode = params->precision;
+  HIP_TRY(ctx, launch_centroid(q0, n, j.cen, s), "centroid");
+  HIP_TRY(ctx, launch_stage(mode, n, q0, p0, target, j.cen, j.sc.k, j.st, j.xc, j.slot(0), s),
+          "stage");
+  if (j.L.nseg > 0)
+    HIP_TRY(ctx, hipMemcpyAsync(j.ckpt_state(0), j.st, 6 * (size_t)n * 8, hipMemcpyDeviceToDevice, s),
+            "checkpoint 0");
+  HIP_TRY(ctx, run_forward(j, 0, T, true, true, s, &ctx->timer), "forward step");
+  HIP_TRY(ctx, launch_loss(mode, n, j.plan.nb, params->lambda, j.sc.bscale, j.st, j.xc, j.cen,
+                           j.h0p, j.ad, j.arec_buf(0), out3, q1, nullptr, ctx->flag, s),
+          "loss");
+  int cur = 0;
+  if (j.L.nseg == 0) {
+    HIP_TRY(ctx, run_adjoint(j, 0, T, &cur, grad, s, &ctx->timer), "adjoint step");
+  } else {
+    const int every = params->ckpt_every;
+    for (int seg = j.L.nseg - 1; seg >= 0; --seg) {
+      const int t0 = seg * every, t1 = std::min(T, t0 + every);
+      if (seg != j.L.nseg - 1) {   // the last segment is still in the ring of slots
+        HIP_TRY(ctx, launch_restore(mode, n, j.ckpt_state(seg), j.sc.k, j.st, j.slot(t0), s),
+                "restore");
+        HIP_TRY(ctx, run_forward(j, t0, t1, false, false, s, &ctx->timer), "recompute step");
+      }
+      HIP_TRY(ctx, run_adjoint(j, t0, t1, &cur, grad, s, &ctx->timer), "adjoint step");
+    }
+  }
+  return LDDMM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -319,9 +358,12 @@ lddmm_status lddmm_ctx_create(int device, lddmm_ctx** out) {
   c->device = device;
   e = hipMalloc(&c->flag, 256);
   if (e == hipSuccess) e = hipMemset(c->flag, 0, 256);
+  if (e == hipSuccess) e = hipHostMalloc(&c->host_done, 2 * sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->poll_ev[0], hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->poll_ev[1], hipEventDisableTiming);
   if (e != hipSuccess) {
-    delete c;
-    return hip_fail(nullptr, e, "flag allocation");
+    lddmm_ctx_destroy(c);
+    return hip_fail(nullptr, e, "context allocation");
   }
   *out = c;
   return LDDMM_OK;
@@ -333,6 +375,10 @@ lddmm_status lddmm_ctx_destroy(lddmm_ctx* ctx) {
   (void)hipDeviceSynchronize();
   if (ctx->ws) (void)hipFree(ctx->ws);
   if (ctx->flag) (void)hipFree(ctx->flag);
+  if (ctx->sws) (void)hipFree(ctx->sws);
+  if (ctx->host_done) (void)hipHostFree(ctx->host_done);
+  for (hipEvent_t& e : ctx->poll_ev)
+    if (e) (void)hipEventDestroy(e);
   ctx->timer.destroy();
   delete ctx;
   return LDDMM_OK;
@@ -371,34 +417,126 @@ lddmm_status lddmm_shoot_grad(lddmm_ctx* ctx, const lddmm_params* params, const 
   Job j;
   lddmm_status st = begin(ctx, params, &j);
   if (st != LDDMM_OK) return st;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  const int n = params->n, T = params->T, mode = params->precision;
-  HIP_TRY(ctx, launch_centroid(q0, n, j.cen, s), "centroid");
-  HIP_TRY(ctx, launch_stage(mode, n, q0, p0, target, j.cen, j.sc.k, j.st, j.xc, j.slot(0), s),
-          "stage");
-  if (j.L.nseg > 0)
-    HIP_TRY(ctx, hipMemcpyAsync(j.ckpt_state(0), j.st, 6 * (size_t)n * 8, hipMemcpyDeviceToDevice, s),
-            "checkpoint 0");
-  HIP_TRY(ctx, run_forward(j, 0, T, true, true, s, &ctx->timer), "forward step");
-  HIP_TRY(ctx, launch_loss(mode, n, j.plan.nb, params->lambda, j.sc.bscale, j.st, j.xc, j.cen,
-                           j.h0p, j.ad, j.arec_buf(0), out3, q1, nullptr, ctx->flag, s),
-          "loss");
-  int cur = 0;
-  if (j.L.nseg == 0) {
-    HIP_TRY(ctx, run_adjoint(j, 0, T, &cur, grad, s, &ctx->timer), "adjoint step");
-  } else {
-    const int every = params->ckpt_every;
-    for (int seg = j.L.nseg - 1; seg >= 0; --seg) {
-      const int t0 = seg * every, t1 = std::min(T, t0 + every);
-      if (seg != j.L.nseg - 1) {   // the last segment is still in the ring of slots
-        HIP_TRY(ctx, launch_restore(mode, n, j.ckpt_state(seg), j.sc.k, j.st, j.slot(t0), s),
-                "restore");
-        HIP_TRY(ctx, run_forward(j, t0, t1, false, false, s, &ctx->timer), "recompute step");
-      }
-      HIP_TRY(ctx, run_adjoint(j, t0, t1, &cur, grad, s, &ctx->timer), "adjoint step");
-    }
-  }
+  return run_grad(ctx, j, q0, p0, target, out3, grad, q1, static_cast<hipStream_t>(stream));
+}
+
+lddmm_status lddmm_solve_opts_default(int32_t precision, lddmm_solve_opts* o) {
+  if (!o) return fail(nullptr, LDDMM_EINVAL, "opts is NULL");
+  if (precision < LDDMM_FP32 || precision > LDDMM_FP64)
+    return fail(nullptr, LDDMM_EINVAL, "unknown precision %d", precision);
+  o->max_iter = 100;
+  o->m = 5;
+  o->max_fev = 20;
+  o->gtol = precision == LDDMM_FP64 ? 1e-8 : 1e-6;
+  o->ftol_rel = 0.0;
+  o->c1 = 1e-4;
+  o->c2 = 0.9;
+  o->init = 0;
   return LDDMM_OK;
+}
+
+lddmm_status lddmm_solve(lddmm_ctx* ctx, const lddmm_params* params, const lddmm_solve_opts* opts,
+                         const double* q0, const double* target, double* p0_inout,
+                         lddmm_solve_result* result, double* trace, void* stream) {
+  if (ctx && (!opts || !q0 || !target || !p0_inout))
+    return fail(ctx, LDDMM_EINVAL, "opts, q0, target and p0_inout must not be NULL");
+  if (ctx) {
+    if (opts->max_iter < 0) return fail(ctx, LDDMM_EINVAL, "max_iter must be >= 0");
+    if (opts->m < 1 || opts->m > kMaxHistory)
+      return fail(ctx, LDDMM_EINVAL, "m must be in 1..%d", kMaxHistory);
+    if (opts->max_fev < 1) return fail(ctx, LDDMM_EINVAL, "max_fev must be >= 1");
+    if (!(opts->c1 > 0.0 && opts->c1 < opts->c2 && opts->c2 < 1.0))
+      return fail(ctx, LDDMM_EINVAL, "need 0 < c1 < c2 < 1");
+    if (!(opts->gtol >= 0.0) || !(opts->ftol_rel >= 0.0))
+      return fail(ctx, LDDMM_EINVAL, "gtol and ftol_rel must be >= 0");
+    if (opts->init < 0 || opts->init > 2) return fail(ctx, LDDMM_EINVAL, "init must be 0, 1 or 2");
+  }
+  Job j;
+  lddmm_status st = begin(ctx, params, &j);
+  if (st != LDDMM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = params->n;
+  const size_t m3 = 3 * (size_t)n;
+
+  // solver workspace: x g d xt gt, S Y, q1, out3, state, result, trace
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off += a256(bytes); return o; };
+  const size_t o_vec = take(5 * m3 * 8), o_hist = take(2 * (size_t)opts->m * m3 * 8);
+  const size_t o_q1 = take(m3 * 8), o_out3 = take(4 * 8), o_state = take(sizeof(LbfgsState));
+  const size_t o_res = take(sizeof(LbfgsResult));
+  const size_t o_trace = take(2 * ((size_t)opts->max_iter + 1) * 8);
+  if (off > ctx->sws_bytes) {
+    HIP_TRY(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize");
+    if (ctx->sws) HIP_TRY(ctx, hipFree(ctx->sws), "hipFree");
+    ctx->sws = nullptr;
+    ctx->sws_bytes = 0;
+    if (hipMalloc(&ctx->sws, off) != hipSuccess) {
+      ctx->sws = nullptr;
+      (void)hipGetLastError();
+      return fail(ctx, LDDMM_ENOMEM, "hipMalloc of %zu bytes (solver) failed", off);
+    }
+    ctx->sws_bytes = off;
+  }
+  LbfgsBufs B{};
+  B.m3 = (int)m3;
+  double* vec = at<double>(ctx->sws, o_vec);
+  B.x = vec; B.g = vec + m3; B.d = vec + 2 * m3; B.xt = vec + 3 * m3; B.gt = vec + 4 * m3;
+  B.S = at<double>(ctx->sws, o_hist);
+  B.Y = B.S + (size_t)opts->m * m3;
+  double* q1 = at<double>(ctx->sws, o_q1);
+  double* out3 = at<double>(ctx->sws, o_out3);
+  B.ft = out3;
+  B.trace = at<double>(ctx->sws, o_trace);
+  LbfgsState* state = at<LbfgsState>(ctx->sws, o_state);
+  LbfgsResult* dres = at<LbfgsResult>(ctx->sws, o_res);
+  LbfgsOpts o{opts->max_iter, opts->m, opts->max_fev, opts->gtol, opts->ftol_rel, opts->c1, opts->c2};
+
+  HIP_TRY(ctx, launch_lbfgs_init(B, state, opts->init, q0, target, p0_inout, params->T, s),
+          "solver init");
+  // Evaluation c and the optimiser step that consumes it are enqueued before
+  // the host waits on evaluation c-1, so the device never idles on the poll;
+  // at most one evaluation after convergence is wasted (its step is a no-op).
+  const long cap = 1 + (long)opts->max_iter * opts->max_fev;
+  for (long c = 0;; ++c) {
+    st = run_grad(ctx, j, q0, B.xt, target, out3, B.gt, nullptr, s);
+    if (st != LDDMM_OK) return st;
+    HIP_TRY(ctx, launch_lbfgs_step(B, state, o, s), "solver step");
+    HIP_TRY(ctx, hipMemcpyAsync(&ctx->host_done[c & 1], &state->done, sizeof(int),
+                                hipMemcpyDeviceToHost, s), "poll copy");
+    HIP_TRY(ctx, hipEventRecord(ctx->poll_ev[c & 1], s), "poll event");
+    if (c >= 1) {
+      HIP_TRY(ctx, hipEventSynchronize(ctx->poll_ev[(c - 1) & 1]), "poll wait");
+      if (ctx->host_done[(c - 1) & 1]) break;
+    }
+    if (c + 1 >= cap) break;
+  }
+  // final evaluation at the accepted iterate, for the reported loss terms and q(1)
+  st = run_grad(ctx, j, q0, B.x, target, out3, B.gt, q1, s);
+  if (st != LDDMM_OK) return st;
+  HIP_TRY(ctx, launch_lbfgs_result(n, q1, target, out3, state, dres, s), "solver result");
+  HIP_TRY(ctx, hipMemcpyAsync(p0_inout, B.x, m3 * 8, hipMemcpyDeviceToDevice, s), "p0 copy");
+  LbfgsResult hr{};
+  HIP_TRY(ctx, hipMemcpyAsync(&hr, dres, sizeof hr, hipMemcpyDeviceToHost, s), "result copy");
+  if (trace)
+    HIP_TRY(ctx, hipMemcpyAsync(trace, B.trace, 2 * ((size_t)opts->max_iter + 1) * 8,
+                                hipMemcpyDeviceToHost, s), "trace copy");
+  HIP_TRY(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+  const lddmm_status rs = hr.status == kConverged ? LDDMM_OK
+                          : hr.status == kNonFinite ? LDDMM_ENONFINITE : LDDMM_ENOTCONV;
+  if (result) {
+    result->loss = hr.loss;
+    result->H0 = hr.H0;
+    result->mismatch = hr.mismatch;
+    result->grad_norm = hr.grad_norm;
+    result->avg_dist = hr.avg_dist;
+    result->max_dist = hr.max_dist;
+    result->iters = hr.iters;
+    result->fevals = hr.fevals;
+    result->status = rs;
+  }
+  if (!hr.done) return fail(ctx, LDDMM_ENOTCONV, "evaluation cap reached");
+  if (rs == LDDMM_ENONFINITE) return fail(ctx, rs, "non-finite loss or gradient");
+  return rs;
 }
 
 lddmm_status lddmm_ctx_set_timing(lddmm_ctx* ctx, int enable) {

@@ -36,6 +36,19 @@ class Timing(ctypes.Structure):
                 ("fwd_launches", ctypes.c_int64), ("adj_launches", ctypes.c_int64)]
 
 
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("m", ctypes.c_int32), ("max_fev", ctypes.c_int32),
+                ("gtol", ctypes.c_double), ("ftol_rel", ctypes.c_double),
+                ("c1", ctypes.c_double), ("c2", ctypes.c_double), ("init", ctypes.c_int32)]
+
+
+class SolveResult(ctypes.Structure):
+    _fields_ = [("loss", ctypes.c_double), ("H0", ctypes.c_double),
+                ("mismatch", ctypes.c_double), ("grad_norm", ctypes.c_double),
+                ("avg_dist", ctypes.c_double), ("max_dist", ctypes.c_double),
+                ("iters", ctypes.c_int32), ("fevals", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
 class LddmmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -59,6 +72,9 @@ def lib():
         L.lddmm_shoot_forward.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp]
         L.lddmm_shoot_grad.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.lddmm_ctx_check.argtypes = [_vp, _vp]
+        L.lddmm_solve_opts_default.argtypes = [ctypes.c_int32, ctypes.POINTER(SolveOpts)]
+        L.lddmm_solve.argtypes = [_vp, ctypes.POINTER(Params), ctypes.POINTER(SolveOpts), _vp, _vp,
+                                  _vp, ctypes.POINTER(SolveResult), _vp, _vp]
         L.lddmm_ctx_set_timing.argtypes = [_vp, ctypes.c_int]
         L.lddmm_ctx_timing.argtypes = [_vp, ctypes.POINTER(Timing), ctypes.c_int]
         L.lddmm_status_string.argtypes = [ctypes.c_int]
@@ -68,7 +84,8 @@ def lib():
         L.lddmm_version.restype = ctypes.c_char_p
         for f in ("lddmm_ctx_create", "lddmm_ctx_destroy", "lddmm_workspace_size",
                   "lddmm_shoot_forward", "lddmm_shoot_grad", "lddmm_ctx_check",
-                  "lddmm_ctx_set_timing", "lddmm_ctx_timing"):
+                  "lddmm_ctx_set_timing", "lddmm_ctx_timing", "lddmm_solve_opts_default",
+                  "lddmm_solve"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -86,6 +103,18 @@ def make_params(n: int, T: int, sigma: float, lam: float, precision="fp32c",
                 ckpt_every: int = 0) -> Params:
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     return Params(int(n), int(T), float(sigma), float(lam), prec, int(ckpt_every))
+
+
+def solve_opts(precision="fp32c", **overrides) -> SolveOpts:
+    """Library defaults for ``precision``, with fields overridden by keyword."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o = SolveOpts()
+    _check(lib().lddmm_solve_opts_default(prec, ctypes.byref(o)))
+    for k, v in overrides.items():
+        if k not in dict(SolveOpts._fields_):
+            raise TypeError(f"unknown solver option {k}")
+        setattr(o, k, v)
+    return o
 
 
 def workspace_size(params: Params) -> int:
@@ -185,6 +214,31 @@ class Context:
                                       q1.data_ptr() if q1 is not None else None,
                                       _stream(stream)), self._h)
         return GradResult(out3[0], out3[1], out3[2], grad, q1)
+
+    def solve(self, q0: torch.Tensor, target: torch.Tensor, T: int, sigma: float, lam: float,
+              precision="fp32c", p0: torch.Tensor | None = None, ckpt_every: int = 0,
+              want_trace: bool = False, stream=None, **opts) -> dict:
+        """L-BFGS registration on the GPU (Alg. 1).  ``opts`` override the
+        library defaults (max_iter, m, max_fev, gtol, ftol_rel, c1, c2, init);
+        passing ``p0`` selects init = 2 (start from it)."""
+        import numpy as np
+        n = q0.shape[0]
+        prm = make_params(n, T, sigma, lam, precision, ckpt_every)
+        if p0 is not None:
+            opts.setdefault("init", 2)
+        o = solve_opts(precision, **opts)
+        out = torch.empty_like(q0) if p0 is None else p0.detach().clone().contiguous()
+        res = SolveResult()
+        tr = np.full(2 * (o.max_iter + 1), np.nan) if want_trace else None
+        rc = lib().lddmm_solve(self._h, ctypes.byref(prm), ctypes.byref(o), _pts(q0, "q0", n),
+                               _pts(target, "target", n), _pts(out, "p0", n), ctypes.byref(res),
+                               tr.ctypes.data if tr is not None else None, _stream(stream))
+        _check(rc, self._h, allow=(OK, ENOTCONV))
+        r = {k: getattr(res, k) for k, _ in SolveResult._fields_}
+        r["p0"] = out
+        if tr is not None:
+            r["trace"] = tr.reshape(-1, 2)[: res.iters + 1]
+        return r
 
     def set_timing(self, enable: bool) -> None:
         """Bracket every pair-kernel launch with HIP events on its stream."""

@@ -1,0 +1,116 @@
+"""torch.autograd.Function over the hand-written adjoint: equal to the C-ABI
+call, checked against finite differences and the oracle, and bitwise
+unchanged when the trajectory is recomputed from checkpoints."""
+import numpy as np
+import pytest
+
+from paper_1907_04839_amd import synth
+
+from conftest import rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_loss_and_grad_equal_the_c_abi_call(gpu_ctx):
+    import torch
+    from paper_1907_04839_amd.autograd import shoot_loss
+    pb = synth.random_problem(301, 900, T=7)
+    p0 = to_dev(pb.p0).requires_grad_(True)
+    L = shoot_loss(p0, to_dev(pb.q0), to_dev(pb.target), pb.T, pb.sigma, pb.lam, "fp32c", 0)
+    L.backward()
+    r = gpu_ctx.shoot_grad(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), pb.T, pb.sigma,
+                           pb.lam, "fp32c")
+    torch.cuda.synchronize()
+    assert L.item() == r.loss.item()
+    assert torch.equal(p0.grad, r.grad)
+
+
+def test_backward_scales_by_the_incoming_gradient():
+    import torch
+    from paper_1907_04839_amd.autograd import shoot_loss
+    pb = synth.random_problem(302, 100, T=3)
+    p0 = to_dev(pb.p0).requires_grad_(True)
+    L = shoot_loss(p0, to_dev(pb.q0), to_dev(pb.target), pb.T, pb.sigma, pb.lam, "fp64", 0)
+    (3.5 * L).backward()
+    g1 = p0.grad.clone()
+    p0.grad = None
+    shoot_loss(p0, to_dev(pb.q0), to_dev(pb.target), pb.T, pb.sigma, pb.lam, "fp64", 0).backward()
+    torch.testing.assert_close(g1, 3.5 * p0.grad, rtol=1e-15, atol=0)
+
+
+def test_fp64_gradient_matches_central_differences():
+    import torch
+    from paper_1907_04839_amd.autograd import shoot_loss
+    pb = synth.random_problem(303, 40, T=5)
+    q0, x = to_dev(pb.q0), to_dev(pb.target)
+    p0 = to_dev(pb.p0).requires_grad_(True)
+    shoot_loss(p0, q0, x, pb.T, pb.sigma, pb.lam, "fp64", 0).backward()
+    g = p0.grad.detach().cpu().numpy()
+    eps = 1e-6
+    fd = np.zeros_like(g)
+    base = to_dev(pb.p0)
+    with torch.no_grad():
+        for i in range(pb.n):
+            for d in range(3):
+                e = torch.zeros_like(base)
+                e[i, d] = eps
+                lp = shoot_loss(base + e, q0, x, pb.T, pb.sigma, pb.lam, "fp64", 0).item()
+                lm = shoot_loss(base - e, q0, x, pb.T, pb.sigma, pb.lam, "fp64", 0).item()
+                fd[i, d] = (lp - lm) / (2 * eps)
+    err = rel_err(g, fd)
+    print(f"[autograd FD n=40] {err:.2e}", flush=True)
+    assert err < 1e-7
+
+
+@pytest.mark.parametrize("mode,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
+def test_sphere_subsample_T100_matches_oracle(orc_mt, mode, tol):
+    """The 16384-landmark sphere workload's settings (sigma 6, T 100,
+    checkpoints every 10 steps) on a seeded 512-landmark subsample."""
+    import torch
+    from paper_1907_04839_amd.autograd import shoot_loss
+    pb = synth.subsample(synth.sphere_autograd(), 512)
+    p0 = to_dev(pb.p0).requires_grad_(True)
+    L = shoot_loss(p0, to_dev(pb.q0), to_dev(pb.target), pb.T, pb.sigma, pb.lam, mode, 10)
+    L.backward()
+    torch.cuda.synchronize()
+    o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, pb.T)
+    el = abs(L.item() - o["loss"]) / abs(o["loss"])
+    eg = rel_err(p0.grad.cpu().numpy(), o["grad"])
+    print(f"[autograd sphere512 T=100 {mode}] loss={el:.2e} grad={eg:.2e}", flush=True)
+    assert el <= tol and eg <= tol
+
+
+def test_automatic_checkpointing_is_bitwise_identical():
+    import torch
+    from paper_1907_04839_amd.autograd import ShootConfig, ShootLoss
+    pb = synth.random_problem(304, 2000, T=30)
+    q0, x = to_dev(pb.q0), to_dev(pb.target)
+    grads = []
+    for budget in (1 << 34, 200_000):        # everything fits / only a ring of ~6 records fits
+        cfg = ShootConfig(pb.T, pb.sigma, pb.lam, "fp32c", "auto", budget)
+        p0 = to_dev(pb.p0).requires_grad_(True)
+        ShootLoss.apply(p0, q0, x, cfg).backward()
+        grads.append(p0.grad.clone())
+    assert ShootConfig(pb.T, pb.sigma, pb.lam, "fp32c", "auto", 200_000).resolve_ckpt(pb.n) > 0
+    torch.cuda.synchronize()
+    assert torch.equal(grads[0], grads[1])
+
+
+def test_torch_optimizer_drives_the_loss_down():
+    import torch
+    from paper_1907_04839_amd.autograd import shoot_loss
+    pb = synth.box_displacement()
+    q0, x = to_dev(pb.q0), to_dev(pb.target)
+    p0 = torch.zeros_like(q0, requires_grad=True)
+    opt = torch.optim.LBFGS([p0], max_iter=20, line_search_fn="strong_wolfe")
+
+    def closure():
+        opt.zero_grad()
+        L = shoot_loss(p0, q0, x, pb.T, pb.sigma, pb.lam, "fp64", 0)
+        L.backward()
+        return L
+
+    L0 = closure().item()
+    opt.step(closure)
+    L1 = shoot_loss(p0, q0, x, pb.T, pb.sigma, pb.lam, "fp64", 0).item()
+    assert L1 < 0.5 * L0

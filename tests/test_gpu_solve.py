@@ -1,0 +1,114 @@
+"""On-device L-BFGS (lddmm_solve) against closed forms and the oracle's own
+L-BFGS, which runs the same algorithm: per-iteration (loss, |g|) traces and
+the final solution (loss, q(1), v0 = K(q0) p0, and p0 where K is well
+conditioned)."""
+import numpy as np
+import pytest
+
+from paper_1907_04839_amd import synth
+
+from conftest import rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def dense_K(q, sigma):
+    from scipy.spatial.distance import cdist
+    return np.exp(-cdist(q, q, "sqeuclidean") / (2.0 * sigma ** 2))
+
+
+def gpu_solve(ctx, pb, mode, **opts):
+    import torch
+    r = ctx.solve(to_dev(pb.q0), to_dev(pb.target), pb.T, pb.sigma, pb.lam, precision=mode,
+                  want_trace=True, **opts)
+    torch.cuda.synchronize()
+    r["p0"] = r["p0"].cpu().numpy()
+    return r
+
+
+def test_single_landmark_closed_form(gpu_ctx):
+    q0 = np.array([[1.0, 2.0, 3.0]])
+    x = np.array([[4.0, 0.0, 3.5]])
+    for lam in (1.0, 10.0):
+        pb = synth.Problem("one", q0, x, np.zeros_like(q0), 3.0, lam, 10)
+        r = gpu_solve(gpu_ctx, pb, "fp64", max_iter=20, gtol=1e-12)
+        p_star = 2 * lam * (x - q0) / (1 + 2 * lam)
+        np.testing.assert_allclose(r["p0"], p_star, rtol=1e-10, atol=1e-12)
+        assert abs(r["loss"] - lam * ((x - q0) ** 2).sum() / (1 + 2 * lam)) < 1e-12
+        assert r["status"] == 0 and r["iters"] <= 3
+
+
+def test_init_modes_and_zero_iterations(gpu_ctx):
+    import torch
+    pb = synth.random_problem(401, 50, T=4)
+    r = gpu_solve(gpu_ctx, pb, "fp64", max_iter=0, init=1)
+    np.testing.assert_allclose(r["p0"], (pb.target - pb.q0) / pb.T, rtol=1e-15, atol=1e-15)
+    p0 = to_dev(pb.p0)
+    r = gpu_ctx.solve(to_dev(pb.q0), to_dev(pb.target), pb.T, pb.sigma, pb.lam, "fp64", p0=p0,
+                      max_iter=0)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(r["p0"].cpu().numpy(), pb.p0)
+    assert r["iters"] == 0 and r["fevals"] == 1
+
+
+def test_box64_fp64_matches_oracle_solver(gpu_ctx, orc_mt):
+    """The 64-landmark box workload, 50 iterations in FP64: same iterates as
+    the oracle's L-BFGS (cond K(q0) ~ 30, so p0 itself is compared)."""
+    pb = synth.box_displacement()
+    g = gpu_solve(gpu_ctx, pb, "fp64", max_iter=pb.iters)
+    o = orc_mt.solve(pb.q0, pb.target, pb.sigma, pb.lam, pb.T, orc_mt.SolveOpts(max_iter=pb.iters))
+    k = min(11, len(o["trace"]), len(g["trace"]))
+    tr = np.abs(g["trace"][:k] - o["trace"][:k]) / np.abs(o["trace"][:k])
+    K = dense_K(pb.q0, pb.sigma)
+    e = dict(loss=abs(g["loss"] - o["loss"]) / o["loss"], p0=rel_err(g["p0"], o["p0"]),
+             v0=rel_err(K @ g["p0"], K @ o["p0"]), trace10=float(tr.max()))
+    print(f"[solve box64 fp64] iters {g['iters']}/{o['iters']} fevals {g['fevals']}/{o['fevals']} "
+          + " ".join(f"{a}={b:.2e}" for a, b in e.items()), flush=True)
+    assert g["iters"] == o["iters"] and g["fevals"] == o["fevals"] and g["status"] == o["status"]
+    assert e["trace10"] < 1e-12 and e["loss"] < 1e-12
+    assert e["p0"] < 1e-9 and e["v0"] < 1e-9
+    assert abs(g["avg_dist"] - o["avg_dist"]) < 1e-9 * o["avg_dist"]
+    assert abs(g["max_dist"] - o["max_dist"]) < 1e-9 * o["max_dist"]
+
+
+@pytest.mark.parametrize("mode", ["fp32c", "fp64"])
+def test_ellipsoid4096_solver_trace_matches_oracle(gpu_ctx, orc_mt, mode):
+    """The 4096-landmark ellipsoid workload (T = 40): the first 10 accepted
+    steps against the oracle's L-BFGS; loss, q(1) and v0 compared (K(q0) is
+    near singular here, so raw p0 is reported, not gated)."""
+    pb = synth.ellipsoid_warp()
+    its = 10
+    g = gpu_solve(gpu_ctx, pb, mode, max_iter=its)
+    gtol = 1e-8 if mode == "fp64" else 1e-6
+    o = orc_mt.solve(pb.q0, pb.target, pb.sigma, pb.lam, pb.T,
+                     orc_mt.SolveOpts(max_iter=its, gtol=gtol))
+    k = min(len(o["trace"]), len(g["trace"]))
+    tr = float((np.abs(g["trace"][:k, 0] - o["trace"][:k, 0]) / np.abs(o["trace"][:k, 0])).max())
+    q1g = orc_mt.shoot_forward(pb.q0, g["p0"], pb.sigma, pb.T)["q1"]
+    q1o = orc_mt.shoot_forward(pb.q0, o["p0"], pb.sigma, pb.T)["q1"]
+    e = dict(loss=abs(g["loss"] - o["loss"]) / o["loss"], q1=rel_err(q1g, q1o),
+             p0=rel_err(g["p0"], o["p0"]), trace_loss=tr)
+    print(f"[solve ellipsoid4096 {mode}] iters {g['iters']}/{o['iters']} fevals "
+          f"{g['fevals']}/{o['fevals']} " + " ".join(f"{a}={b:.2e}" for a, b in e.items()),
+          flush=True)
+    tol = 1e-10 if mode == "fp64" else 1e-5
+    assert g["iters"] == o["iters"]
+    assert e["trace_loss"] < tol and e["loss"] < tol and e["q1"] < tol
+
+
+def test_solver_is_bitwise_reproducible(gpu_ctx):
+    pb = synth.random_problem(402, 700, T=6)
+    a = gpu_solve(gpu_ctx, pb, "fp32c", max_iter=15)
+    b = gpu_solve(gpu_ctx, pb, "fp32c", max_iter=15)
+    np.testing.assert_array_equal(a["p0"], b["p0"])
+    assert a["loss"] == b["loss"] and a["fevals"] == b["fevals"]
+
+
+def test_invalid_solver_options(gpu_ctx):
+    from paper_1907_04839_amd import lddmm
+    pb = synth.random_problem(403, 10, T=2)
+    for bad in (dict(m=0), dict(m=17), dict(max_fev=0), dict(c1=0.95), dict(init=3),
+                dict(max_iter=-1)):
+        with pytest.raises(lddmm.LddmmError) as e:
+            gpu_ctx.solve(to_dev(pb.q0), to_dev(pb.target), 2, 1.0, 1.0, "fp64", **bad)
+        assert e.value.status == lddmm.EINVAL
