@@ -153,6 +153,75 @@ lddmm_status lddmm_solve(lddmm_ctx* ctx, const lddmm_params* params, const lddmm
                          const double* q0, const double* target, double* p0_inout,
                          lddmm_solve_result* result, double* trace, void* stream);
 
+/* ---- Serving: continuous batching of registrations ----------------------
+ * A server owns one GPU stream, a preallocated HBM arena and a worker
+ * thread.  Submitted registrations (host inputs, copied at submit) are
+ * admitted first come first served whenever a slot is free and the job's
+ * device footprint (lddmm_server_job_footprint) fits the arena; every running
+ * job keeps its trajectory, adjoint and L-BFGS state on the device.  Each
+ * round advances all running jobs by one loss+gradient evaluation and one
+ * optimiser step through batched pair-sum launches replayed from a captured
+ * hipGraph; jobs join at the next round after admission and leave when their
+ * optimiser finishes.  A job's result does not depend on the other jobs in
+ * the batch (same decomposition, same summation order).  All jobs of a
+ * server share T and the precision. */
+typedef struct lddmm_server lddmm_server;
+
+typedef struct {
+  int32_t device;
+  int32_t max_slots;          /* jobs on the GPU at once, 1..1024 */
+  int32_t max_n;              /* largest n accepted */
+  int32_t T;                  /* Euler steps of every job */
+  int32_t precision;          /* lddmm_precision of every job */
+  size_t hbm_budget_bytes;    /* arena for job state, allocated at create */
+} lddmm_server_config;
+
+typedef struct {
+  double submit_s, admit_s, done_s;   /* seconds on the server's steady clock */
+} lddmm_job_times;
+
+typedef struct {
+  int64_t queued, running, completed;
+  int64_t rounds;             /* batched rounds launched */
+  int64_t job_evaluations;    /* loss+gradient evaluations summed over jobs */
+  size_t hbm_used_bytes, hbm_budget_bytes;
+} lddmm_server_stats;
+
+/* Errors: EINVAL, ENOMEM (arena), EDEVICE. */
+lddmm_status lddmm_server_create(const lddmm_server_config* cfg, lddmm_server** out);
+
+/* Device bytes one job of n landmarks and m curvature pairs occupies. */
+lddmm_status lddmm_server_job_footprint(const lddmm_server_config* cfg, int32_t n, int32_t m,
+                                        size_t* bytes);
+
+/* Queues a registration.  q0, target (and p0 when opts->init == 2) are HOST
+ * [n][3] FP64 arrays, copied before the call returns.  params->T and
+ * ->precision must equal the server's; ckpt_every is ignored.
+ * Errors: EINVAL, ENOMEM (footprint larger than the whole arena), EDEVICE. */
+lddmm_status lddmm_server_submit(lddmm_server* srv, const lddmm_params* params,
+                                 const lddmm_solve_opts* opts, const double* q0,
+                                 const double* target, const double* p0, int64_t* job_id);
+
+/* Result of a job: LDDMM_EBUSY while it is queued or running; once done, the
+ * solve status (OK, ENOTCONV, ENONFINITE) with p0_out ([n][3] host, may be
+ * NULL), result and times filled, after which the id is released.
+ * EINVAL for an unknown id, EDEVICE if the server failed. */
+lddmm_status lddmm_server_poll(lddmm_server* srv, int64_t job_id, double* p0_out,
+                               lddmm_solve_result* result, lddmm_job_times* times);
+
+/* Blocks until the job can be polled (timeout_s < 0: no limit); EBUSY on
+ * timeout, EINVAL for an unknown id. */
+lddmm_status lddmm_server_wait(lddmm_server* srv, int64_t job_id, double timeout_s);
+
+lddmm_status lddmm_server_stats_get(lddmm_server* srv, lddmm_server_stats* out);
+
+/* Detail of the server's last error. */
+const char* lddmm_server_last_error(lddmm_server* srv);
+
+/* Stops the worker after its current round, drops queued and unfinished
+ * jobs and frees everything.  NULL is accepted. */
+lddmm_status lddmm_server_destroy(lddmm_server* srv);
+
 /* Waits for the context's work on `stream` and reports whether any call
  * since the last check produced a non-finite loss (then ENONFINITE, and the
  * flag is cleared).  Errors: EINVAL, EDEVICE. */

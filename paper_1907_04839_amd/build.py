@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblddmm.so")
 
-SOURCES = ["shoot_kernels.hip", "lbfgs.hip", "lddmm_api.cpp"]
+SOURCES = ["shoot_kernels.hip", "lbfgs.hip", "lddmm_api.cpp", "serve.cpp"]
 
 # Packed FP32 instructions are switched off for the device code.
 HIPCC_FLAGS = [

@@ -72,6 +72,14 @@ __device__ double cubic_step(double a0, double f0, double d0, double a1, double 
   return a;
 }
 
+// Keep q(1) and {L, H0, mismatch} of the point just accepted, so a finished
+// job reports them without another evaluation.
+__device__ __forceinline__ void snapshot(const LbfgsBufs& B) {
+  if (!B.q1t) return;
+  for (int k = threadIdx.x; k < B.m3; k += kThreads) B.q1a[k] = B.q1t[k];
+  if (threadIdx.x < 3) B.out3a[threadIdx.x] = B.ft[threadIdx.x];
+}
+
 // New search direction from g and the history; sets d0, the first trial step
 // and x_t.  Called by every thread; st is the workgroup's shared copy of the
 // state, read by all threads and written by thread 0 only, between barriers.
@@ -151,6 +159,7 @@ __device__ void accept(const LbfgsBufs& B, const LbfgsOpts& o, LbfgsState& st, d
     B.x[k] = B.xt[k];
     B.g[k] = B.gt[k];
   }
+  snapshot(B);
   __syncthreads();
   const double gnorm = sqrt(block_dot(B.g, B.g, m3, red));
   const double xnorm = sqrt(block_dot(B.x, B.x, m3, red));
@@ -204,12 +213,10 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_init(LbfgsBufs B, LbfgsState
 }
 
 // Consumes the evaluation at x_t (loss *B.ft, gradient B.gt) and prepares the
-// next trial point, or sets done.
-__global__ __launch_bounds__(kThreads) void k_lbfgs_step(LbfgsBufs B, LbfgsState* state,
-                                                         LbfgsOpts o) {
-  __shared__ double red[kThreads];
-  __shared__ LbfgsState st;
-  __shared__ int action;      // 0 accept, 1 new trial at st.a, 2 failed search
+// next trial point, or sets done.  st and action live in LDS.
+__device__ void step_body(const LbfgsBufs& B, LbfgsState* state, const LbfgsOpts& o,
+                          double* red, LbfgsState& st, int& action) {
+  // action: 0 accept, 1 new trial at st.a, 2 failed search
   if (threadIdx.x == 0) st = *state;
   __syncthreads();
   if (st.done) return;
@@ -219,6 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_step(LbfgsBufs B, LbfgsState
 
   if (st.phase == kInit) {
     for (int k = threadIdx.x; k < m3; k += kThreads) B.g[k] = B.gt[k];
+    snapshot(B);
     __syncthreads();
     const double gg = block_dot(B.g, B.g, m3, red);
     const double xx = block_dot(B.x, B.x, m3, red);
@@ -291,6 +299,28 @@ __global__ __launch_bounds__(kThreads) void k_lbfgs_step(LbfgsBufs B, LbfgsState
   if (threadIdx.x == 0) *state = st;
 }
 
+__global__ __launch_bounds__(kThreads) void k_lbfgs_step(LbfgsBufs B, LbfgsState* state,
+                                                         LbfgsOpts o) {
+  __shared__ double red[kThreads];
+  __shared__ LbfgsState st;
+  __shared__ int action;
+  step_body(B, state, o, red, st, action);
+}
+
+__global__ __launch_bounds__(kThreads) void k_lbfgs_step_batch(const LbfgsJob* __restrict__ J) {
+  __shared__ double red[kThreads];
+  __shared__ LbfgsState st;
+  __shared__ int action;
+  const LbfgsJob& j = J[blockIdx.x];
+  if (!j.active) return;
+  step_body(j.B, j.state, j.o, red, st, action);
+}
+
+__global__ void k_gather_done(const LbfgsJob* __restrict__ J, int max_slots, int* __restrict__ done) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < max_slots) done[k] = J[k].active ? J[k].state->done : 0;
+}
+
 // Result of a finished solve: AverageDist / MaxDist of q(1) against x
 // (Sec. 3.1) from the final evaluation, and the solver's counters.
 __global__ __launch_bounds__(kThreads) void k_lbfgs_result(int n, const double* __restrict__ q1,
@@ -341,6 +371,16 @@ hipError_t launch_lbfgs_init(const LbfgsBufs& B, LbfgsState* state, int init, co
 hipError_t launch_lbfgs_step(const LbfgsBufs& B, LbfgsState* state, const LbfgsOpts& o,
                              hipStream_t s) {
   k_lbfgs_step<<<1, kThreads, 0, s>>>(B, state, o);
+  return hipGetLastError();
+}
+
+hipError_t launch_lbfgs_step_batch(const LbfgsJob* jobs, int max_slots, hipStream_t s) {
+  k_lbfgs_step_batch<<<max_slots, kThreads, 0, s>>>(jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_done(const LbfgsJob* jobs, int max_slots, int* done, hipStream_t s) {
+  k_gather_done<<<(max_slots + 255) / 256, 256, 0, s>>>(jobs, max_slots, done);
   return hipGetLastError();
 }
 

@@ -31,8 +31,19 @@ struct LbfgsBufs {
   int m3;
   double *x, *g, *d, *xt, *gt;             // iterate, gradient, direction, trial point and its gradient
   double *S, *Y;                           // [m][m3] curvature pairs
-  const double* ft;                        // loss at the trial point (device scalar)
+  const double* ft;                        // {L, H0, mismatch} at the trial point (device)
   double* trace;                           // optional [max_iter+1][2] (loss, |g|) per accepted step
+  const double* q1t;                       // optional: q(1) at the trial point, [m3]
+  double* q1a;                             // with q1t: q(1) at the accepted point
+  double* out3a;                           // with q1t: {L, H0, mismatch} at the accepted point
+};
+
+// One job of a batched optimiser step.
+struct LbfgsJob {
+  int active;
+  LbfgsBufs B;
+  LbfgsState* state;
+  LbfgsOpts o;
 };
 
 struct LbfgsResult {
@@ -44,6 +55,10 @@ hipError_t launch_lbfgs_init(const LbfgsBufs& B, LbfgsState* state, int init, co
                              const double* x, const double* p_in, int T, hipStream_t s);
 hipError_t launch_lbfgs_step(const LbfgsBufs& B, LbfgsState* state, const LbfgsOpts& o,
                              hipStream_t s);
+// One workgroup per slot; inactive slots return at once.
+hipError_t launch_lbfgs_step_batch(const LbfgsJob* jobs, int max_slots, hipStream_t s);
+// done[k] = the optimiser of slot k has finished (0 for empty slots).
+hipError_t launch_gather_done(const LbfgsJob* jobs, int max_slots, int* done, hipStream_t s);
 hipError_t launch_lbfgs_result(int n, const double* q1, const double* x, const double* out3,
                                const LbfgsState* state, LbfgsResult* res, hipStream_t s);
 

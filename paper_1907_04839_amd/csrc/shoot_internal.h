@@ -92,4 +92,36 @@ hipError_t launch_forward_out(int n, int nb, const double* st, const double* cen
                               const double* h0_part, double* H0, double* q1, double* p1,
                               hipStream_t s);
 
+// One registration of a batched launch, as the batched kernels see it.  All
+// jobs of a batch share T and the precision; the decomposition of every job
+// is one workgroup of 16 waves per 64-landmark i-block and no j split, so a
+// job's results do not depend on which other jobs share the launch.
+struct BatchJob {
+  int active;               // the slot holds a job
+  int n, nb;
+  double lambda;
+  Scales sc;
+  const double* q0;         // [n][3] template
+  const double* p0;         // [n][3] momentum to evaluate (the optimiser's trial point)
+  const int* done;          // the job's optimiser has finished: skip it
+  double *cen, *st, *ad, *hp0, *xc, *h0p, *out3;
+  void *traj, *arec;        // (T+1) point records, two adjoint record buffers
+  double* q1;               // [n][3] q(1) of the latest evaluation
+  double* grad;             // [n][3] gradient of the latest evaluation
+  int* flag;                // non-finite flag
+};
+
+constexpr int kBatchWaves = 16;
+
+// Launch shapes of a batch of at most max_slots jobs with n <= max_n:
+// stage (max_n/256, max_slots), pair kernels `capacity` workgroups (one per
+// (job, i-block) item; items beyond *nitems exit), loss max_slots.
+hipError_t launch_stage_batch(int mode, const BatchJob* jobs, int max_slots, int max_n,
+                              hipStream_t s);
+hipError_t launch_fwd_batch(int mode, const BatchJob* jobs, const int2* items, const int* nitems,
+                            int capacity, int t, hipStream_t s);
+hipError_t launch_loss_batch(int mode, const BatchJob* jobs, int max_slots, hipStream_t s);
+hipError_t launch_adj_batch(int mode, const BatchJob* jobs, const int2* items, const int* nitems,
+                            int capacity, int t, int T, hipStream_t s);
+
 }  // namespace lddmm

@@ -43,8 +43,32 @@ struct alignas(8 * sizeof(R)) Rec {
   R x, y, z, u, px, py, pz, w;
 };
 
+// Pointers that arrive through a descriptor in memory carry no address
+// space; the pair loops read records through a global (address space 1)
+// pointer so that wave-uniform loads can become scalar loads.
+template <typename T>
+using GlobalPtr = const __attribute__((address_space(1))) T*;
+
+template <typename T>
+__device__ __forceinline__ GlobalPtr<T> global_ptr(const T* p) {
+  return (GlobalPtr<T>)p;
+}
+
 template <typename R, bool COMP>
 struct AccOf { using type = double; };
+
+template <typename R>
+struct Rec;
+
+// Field-wise copy of record j (an address-space-qualified struct cannot be
+// copied as a whole); adjacent scalar loads merge into one wide load.
+template <typename R>
+__device__ __forceinline__ Rec<R> load_rec(GlobalPtr<Rec<R>> p, int j) {
+  Rec<R> r;
+  r.x = p[j].x; r.y = p[j].y; r.z = p[j].z; r.u = p[j].u;
+  r.px = p[j].px; r.py = p[j].py; r.pz = p[j].pz; r.w = p[j].w;
+  return r;
+}
 template <>
 struct AccOf<float, false> { using type = float; };
 
@@ -66,12 +90,13 @@ __device__ __forceinline__ Rec<R> make_rec(double x, double y, double z, double 
 //   h[3..5] += sum_j g_ij (p_i . p_j) (kq_i - kq_j)  (Hq up to the factor -c/k)
 // ---------------------------------------------------------------------------
 template <typename R>
-__device__ __forceinline__ void fwd_range(const Rec<R>* __restrict__ X, const Rec<R>& ri, int j0,
+__device__ __forceinline__ void fwd_range(const Rec<R>* __restrict__ Xp, const Rec<R>& ri, int j0,
                                           int j1, R h[6]) {
+  const GlobalPtr<Rec<R>> X = global_ptr(Xp);
   R hp0 = h[0], hp1 = h[1], hp2 = h[2], hq0 = h[3], hq1 = h[4], hq2 = h[5];
 #pragma unroll 4
   for (int j = j0; j < j1; ++j) {
-    const Rec<R> rj = X[j];
+    const Rec<R> rj = load_rec<R>(X, j);
     const R dx = ri.x - rj.x, dy = ri.y - rj.y, dz = ri.z - rj.z;
     R r2 = dx * dx;
     r2 = fma(dy, dy, r2);
@@ -100,15 +125,17 @@ __device__ __forceinline__ void fwd_range(const Rec<R>* __restrict__ X, const Re
 // and A = (c/k)(A1/kappa - A2).
 // ---------------------------------------------------------------------------
 template <typename R>
-__device__ __forceinline__ void adj_range(const Rec<R>* __restrict__ X,
-                                          const Rec<R>* __restrict__ Y, const Rec<R>& ri,
+__device__ __forceinline__ void adj_range(const Rec<R>* __restrict__ Xp,
+                                          const Rec<R>* __restrict__ Yp, const Rec<R>& ri,
                                           const Rec<R>& yi, int j0, int j1, R h[9]) {
+  const GlobalPtr<Rec<R>> X = global_ptr(Xp);
+  const GlobalPtr<Rec<R>> Y = global_ptr(Yp);
   R a10 = h[0], a11 = h[1], a12 = h[2], a20 = h[3], a21 = h[4], a22 = h[5];
   R b0 = h[6], b1 = h[7], b2 = h[8];
 #pragma unroll 2
   for (int j = j0; j < j1; ++j) {
-    const Rec<R> rj = X[j];
-    const Rec<R> yj = Y[j];
+    const Rec<R> rj = load_rec<R>(X, j);
+    const Rec<R> yj = load_rec<R>(Y, j);
     const R dx = ri.x - rj.x, dy = ri.y - rj.y, dz = ri.z - rj.z;
     R r2 = dx * dx;
     r2 = fma(dy, dy, r2);
@@ -259,15 +286,17 @@ __device__ __forceinline__ void adj_finish(const AdjArgs& A, int ib, int lane, A
 // ---------------------------------------------------------------------------
 // pair kernels
 // ---------------------------------------------------------------------------
+// One workgroup's share of a pair-sum step: i-block ib (64 landmarks, one
+// per lane) against j-chunk s, split over the W waves.  With S == 1 the sums
+// are final and wave 0 applies the Euler update; otherwise the workgroup
+// writes its partial for the combine kernel.  red: W*C*64 accumulators of LDS.
 template <typename R, bool COMP, int W>
-__global__ __launch_bounds__(64 * W) void k_fwd(FwdArgs A) {
+__device__ __forceinline__ void fwd_block(const FwdArgs& A, int ib, int s,
+                                          typename AccOf<R, COMP>::type* red) {
   using Acc = typename AccOf<R, COMP>::type;
   constexpr int NC = 6;
-  __shared__ Acc red[W * NC * 64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int ib = blockIdx.x / A.S;
-  const int s = blockIdx.x - ib * A.S;
   const Rec<R>* __restrict__ X = static_cast<const Rec<R>*>(A.rec_t);
   const Rec<R> ri = X[min(ib * 64 + lane, A.n - 1)];
   const int jb = s * A.chunk;
@@ -280,10 +309,11 @@ __global__ __launch_bounds__(64 * W) void k_fwd(FwdArgs A) {
   wave_sums<R, COMP, NC>(j0, j1, o, [&](int a, int b, auto* h) { fwd_range<R>(X, ri, a, b, h); });
   block_combine<Acc, NC, W>(red, o, w, lane);
   if (A.S == 1) {
-    if (w != 0) return;
-    double h[NC];
-    for (int c = 0; c < NC; ++c) h[c] = red[c * 64 + lane];
-    fwd_finish<R>(A, ib, lane, v, h, h + 3);
+    if (w == 0) {
+      double h[NC];
+      for (int c = 0; c < NC; ++c) h[c] = red[c * 64 + lane];
+      fwd_finish<R>(A, ib, lane, v, h, h + 3);
+    }
   } else {
     Acc* P = static_cast<Acc*>(A.partial);
     for (int idx = threadIdx.x; idx < NC * 64; idx += 64 * W) {
@@ -294,14 +324,12 @@ __global__ __launch_bounds__(64 * W) void k_fwd(FwdArgs A) {
 }
 
 template <typename R, bool COMP, int W>
-__global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
+__device__ __forceinline__ void adj_block(const AdjArgs& A, int ib, int s,
+                                          typename AccOf<R, COMP>::type* red) {
   using Acc = typename AccOf<R, COMP>::type;
   constexpr int NC = 9;
-  __shared__ Acc red[W * NC * 64];
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int ib = blockIdx.x / A.S;
-  const int s = blockIdx.x - ib * A.S;
   const Rec<R>* __restrict__ X = static_cast<const Rec<R>*>(A.rec_t);
   const Rec<R>* __restrict__ Y = static_cast<const Rec<R>*>(A.arec);
   const int ic = min(ib * 64 + lane, A.n - 1);
@@ -318,10 +346,11 @@ __global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
                          [&](int a, int b, auto* h) { adj_range<R>(X, Y, ri, yi, a, b, h); });
   block_combine<Acc, NC, W>(red, o, w, lane);
   if (A.S == 1) {
-    if (w != 0) return;
-    double h[NC];
-    for (int c = 0; c < NC; ++c) h[c] = red[c * 64 + lane];
-    adj_finish<R>(A, ib, lane, v, h);
+    if (w == 0) {
+      double h[NC];
+      for (int c = 0; c < NC; ++c) h[c] = red[c * 64 + lane];
+      adj_finish<R>(A, ib, lane, v, h);
+    }
   } else {
     Acc* P = static_cast<Acc*>(A.partial);
     for (int idx = threadIdx.x; idx < NC * 64; idx += 64 * W) {
@@ -329,6 +358,18 @@ __global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
       if (i < A.n) P[((size_t)s * NC + c) * A.n + i] = red[idx];
     }
   }
+}
+
+template <typename R, bool COMP, int W>
+__global__ __launch_bounds__(64 * W) void k_fwd(FwdArgs A) {
+  __shared__ typename AccOf<R, COMP>::type red[W * 6 * 64];
+  fwd_block<R, COMP, W>(A, blockIdx.x / A.S, blockIdx.x % A.S, red);
+}
+
+template <typename R, bool COMP, int W>
+__global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
+  __shared__ typename AccOf<R, COMP>::type red[W * 9 * 64];
+  adj_block<R, COMP, W>(A, blockIdx.x / A.S, blockIdx.x % A.S, red);
 }
 
 // Split path (S > 1): combine the S workgroup partials in chunk order, then
@@ -454,13 +495,14 @@ __device__ __forceinline__ double sum_h0(const double* __restrict__ h0_part, int
 }
 
 template <typename R>
-__global__ __launch_bounds__(kLossThreads) void k_loss(
-    int n, int nb, double lambda, double bscale, const double* __restrict__ st,
-    const double* __restrict__ xc, const double* __restrict__ cen,
-    const double* __restrict__ h0_part, double* __restrict__ ad, Rec<R>* __restrict__ arec0,
-    double* __restrict__ out3, double* __restrict__ q1, double* __restrict__ p1,
-    int* __restrict__ flag) {
-  __shared__ double red[kLossThreads];
+__device__ __forceinline__ void loss_body(int n, int nb, double lambda, const double* __restrict__ st,
+                                          const double* __restrict__ xc,
+                                          const double* __restrict__ cen,
+                                          const double* __restrict__ h0_part,
+                                          double* __restrict__ ad, Rec<R>* __restrict__ arec0,
+                                          double* __restrict__ out3, double* __restrict__ q1,
+                                          double* __restrict__ p1, int* __restrict__ flag,
+                                          double* red) {
   double mis = 0.0;
   for (int i = threadIdx.x; i < n; i += kLossThreads) {
     double a[3];
@@ -487,6 +529,16 @@ __global__ __launch_bounds__(kLossThreads) void k_loss(
   }
 }
 
+template <typename R>
+__global__ __launch_bounds__(kLossThreads) void k_loss(
+    int n, int nb, double lambda, const double* __restrict__ st, const double* __restrict__ xc,
+    const double* __restrict__ cen, const double* __restrict__ h0_part, double* __restrict__ ad,
+    Rec<R>* __restrict__ arec0, double* __restrict__ out3, double* __restrict__ q1,
+    double* __restrict__ p1, int* __restrict__ flag) {
+  __shared__ double red[kLossThreads];
+  loss_body<R>(n, nb, lambda, st, xc, cen, h0_part, ad, arec0, out3, q1, p1, flag, red);
+}
+
 __global__ __launch_bounds__(kLossThreads) void k_forward_out(
     int n, int nb, const double* __restrict__ st, const double* __restrict__ cen,
     const double* __restrict__ h0_part, double* __restrict__ H0, double* __restrict__ q1,
@@ -499,6 +551,87 @@ __global__ __launch_bounds__(kLossThreads) void k_forward_out(
     }
   const double h = sum_h0(h0_part, nb, red);
   if (threadIdx.x == 0 && H0) *H0 = h;
+}
+
+// ---------------------------------------------------------------------------
+// batched kernels: several registrations per launch
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool job_live(const BatchJob& b) { return b.active && *b.done == 0; }
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_stage_batch(const BatchJob* __restrict__ J) {
+  const BatchJob& b = J[blockIdx.y];
+  if (!job_live(b)) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const int n = b.n;
+  double q[3], p[3];
+  for (int c = 0; c < 3; ++c) {
+    q[c] = b.q0[3 * i + c] - b.cen[c];
+    p[c] = b.p0[3 * i + c];
+    b.st[c * n + i] = q[c];
+    b.st[(3 + c) * n + i] = p[c];
+  }
+  const double k = b.sc.k;
+  static_cast<Rec<R>*>(b.traj)[i] = make_rec<R>(k * q[0], k * q[1], k * q[2], p[0], p[1], p[2]);
+}
+
+template <typename R>
+__device__ __forceinline__ FwdArgs batch_fwd_args(const BatchJob& b, int t) {
+  FwdArgs A{};
+  A.n = b.n; A.nb = b.nb; A.S = 1; A.chunk = b.n; A.wchunk = (b.n + kBatchWaves - 1) / kBatchWaves;
+  A.sc = b.sc;
+  A.rec_t = static_cast<const Rec<R>*>(b.traj) + (size_t)t * b.n;
+  A.rec_t1 = static_cast<Rec<R>*>(b.traj) + (size_t)(t + 1) * b.n;
+  A.st = b.st;
+  A.hp0 = t == 0 ? b.hp0 : nullptr;
+  A.h0_part = t == 0 ? b.h0p : nullptr;
+  return A;
+}
+
+template <typename R, bool COMP>
+__global__ __launch_bounds__(64 * kBatchWaves) void k_fwd_batch(const BatchJob* __restrict__ J,
+                                                                const int2* __restrict__ items,
+                                                                const int* __restrict__ nitems,
+                                                                int t) {
+  __shared__ typename AccOf<R, COMP>::type red[kBatchWaves * 6 * 64];
+  if ((int)blockIdx.x >= *nitems) return;
+  const int2 it = items[blockIdx.x];
+  const BatchJob& b = J[it.x];
+  if (!job_live(b)) return;
+  fwd_block<R, COMP, kBatchWaves>(batch_fwd_args<R>(b, t), it.y, 0, red);
+}
+
+template <typename R, bool COMP>
+__global__ __launch_bounds__(64 * kBatchWaves) void k_adj_batch(const BatchJob* __restrict__ J,
+                                                                const int2* __restrict__ items,
+                                                                const int* __restrict__ nitems,
+                                                                int t, int T) {
+  __shared__ typename AccOf<R, COMP>::type red[kBatchWaves * 9 * 64];
+  if ((int)blockIdx.x >= *nitems) return;
+  const int2 it = items[blockIdx.x];
+  const BatchJob& b = J[it.x];
+  if (!job_live(b)) return;
+  AdjArgs A{};
+  A.n = b.n; A.nb = b.nb; A.S = 1; A.chunk = b.n; A.wchunk = (b.n + kBatchWaves - 1) / kBatchWaves;
+  A.sc = b.sc;
+  const int cur = (T - 1 - t) & 1;   // the loss kernel fills adjoint buffer 0 for t = T-1
+  A.rec_t = static_cast<const Rec<R>*>(b.traj) + (size_t)t * b.n;
+  A.arec = static_cast<const Rec<R>*>(b.arec) + (size_t)cur * b.n;
+  A.arec_next = static_cast<Rec<R>*>(b.arec) + (size_t)(cur ^ 1) * b.n;
+  A.ad = b.ad;
+  A.hp0 = b.hp0;
+  A.grad = t == 0 ? b.grad : nullptr;
+  adj_block<R, COMP, kBatchWaves>(A, it.y, 0, red);
+}
+
+template <typename R>
+__global__ __launch_bounds__(kLossThreads) void k_loss_batch(const BatchJob* __restrict__ J) {
+  __shared__ double red[kLossThreads];
+  const BatchJob& b = J[blockIdx.x];
+  if (!job_live(b)) return;
+  loss_body<R>(b.n, b.nb, b.lambda, b.st, b.xc, b.cen, b.h0p, b.ad, static_cast<Rec<R>*>(b.arec),
+               b.out3, b.q1, nullptr, b.flag, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -645,11 +778,12 @@ hipError_t launch_loss(int mode, int n, int nb, double lambda, double bscale, co
                        const double* xc, const double* cen, const double* h0_part, double* ad,
                        void* arec0, double* out3, double* q1, double* p1, int* flag,
                        hipStream_t s) {
+  (void)bscale;   // the terminal b is 0, so its scaled record is 0 too
   if (mode == kFP64)
-    k_loss<double><<<1, kLossThreads, 0, s>>>(n, nb, lambda, bscale, st, xc, cen, h0_part, ad,
+    k_loss<double><<<1, kLossThreads, 0, s>>>(n, nb, lambda, st, xc, cen, h0_part, ad,
                                               static_cast<Rec<double>*>(arec0), out3, q1, p1, flag);
   else
-    k_loss<float><<<1, kLossThreads, 0, s>>>(n, nb, lambda, bscale, st, xc, cen, h0_part, ad,
+    k_loss<float><<<1, kLossThreads, 0, s>>>(n, nb, lambda, st, xc, cen, h0_part, ad,
                                              static_cast<Rec<float>*>(arec0), out3, q1, p1, flag);
   return hipGetLastError();
 }
@@ -658,6 +792,44 @@ hipError_t launch_forward_out(int n, int nb, const double* st, const double* cen
                               const double* h0_part, double* H0, double* q1, double* p1,
                               hipStream_t s) {
   k_forward_out<<<1, kLossThreads, 0, s>>>(n, nb, st, cen, h0_part, H0, q1, p1);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage_batch(int mode, const BatchJob* jobs, int max_slots, int max_n,
+                              hipStream_t s) {
+  const dim3 grid((max_n + 255) / 256, max_slots);
+  if (mode == kFP64) k_stage_batch<double><<<grid, 256, 0, s>>>(jobs);
+  else k_stage_batch<float><<<grid, 256, 0, s>>>(jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_fwd_batch(int mode, const BatchJob* jobs, const int2* items, const int* nitems,
+                            int capacity, int t, hipStream_t s) {
+  const int threads = 64 * kBatchWaves;
+  switch (mode) {
+    case kFP32: k_fwd_batch<float, false><<<capacity, threads, 0, s>>>(jobs, items, nitems, t); break;
+    case kFP32Comp: k_fwd_batch<float, true><<<capacity, threads, 0, s>>>(jobs, items, nitems, t); break;
+    case kFP64: k_fwd_batch<double, false><<<capacity, threads, 0, s>>>(jobs, items, nitems, t); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_batch(int mode, const BatchJob* jobs, const int2* items, const int* nitems,
+                            int capacity, int t, int T, hipStream_t s) {
+  const int threads = 64 * kBatchWaves;
+  switch (mode) {
+    case kFP32: k_adj_batch<float, false><<<capacity, threads, 0, s>>>(jobs, items, nitems, t, T); break;
+    case kFP32Comp: k_adj_batch<float, true><<<capacity, threads, 0, s>>>(jobs, items, nitems, t, T); break;
+    case kFP64: k_adj_batch<double, false><<<capacity, threads, 0, s>>>(jobs, items, nitems, t, T); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_loss_batch(int mode, const BatchJob* jobs, int max_slots, hipStream_t s) {
+  if (mode == kFP64) k_loss_batch<double><<<max_slots, kLossThreads, 0, s>>>(jobs);
+  else k_loss_batch<float><<<max_slots, kLossThreads, 0, s>>>(jobs);
   return hipGetLastError();
 }
 

@@ -49,6 +49,24 @@ class SolveResult(ctypes.Structure):
                 ("iters", ctypes.c_int32), ("fevals", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32),
+                ("max_n", ctypes.c_int32), ("T", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
+class JobTimes(ctypes.Structure):
+    _fields_ = [("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("done_s", ctypes.c_double)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("job_evaluations", ctypes.c_int64), ("hbm_used_bytes", ctypes.c_size_t),
+                ("hbm_budget_bytes", ctypes.c_size_t)]
+
+
 class LddmmError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{msg} (status {status})")
@@ -72,6 +90,18 @@ def lib():
         L.lddmm_shoot_forward.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp]
         L.lddmm_shoot_grad.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.lddmm_ctx_check.argtypes = [_vp, _vp]
+        L.lddmm_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]
+        L.lddmm_server_job_footprint.argtypes = [ctypes.POINTER(ServerConfig), ctypes.c_int32,
+                                                 ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+        L.lddmm_server_submit.argtypes = [_vp, ctypes.POINTER(Params), ctypes.POINTER(SolveOpts),
+                                          _vp, _vp, _vp, ctypes.POINTER(ctypes.c_int64)]
+        L.lddmm_server_poll.argtypes = [_vp, ctypes.c_int64, _vp, ctypes.POINTER(SolveResult),
+                                        ctypes.POINTER(JobTimes)]
+        L.lddmm_server_wait.argtypes = [_vp, ctypes.c_int64, ctypes.c_double]
+        L.lddmm_server_stats_get.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+        L.lddmm_server_last_error.argtypes = [_vp]
+        L.lddmm_server_last_error.restype = ctypes.c_char_p
+        L.lddmm_server_destroy.argtypes = [_vp]
         L.lddmm_solve_opts_default.argtypes = [ctypes.c_int32, ctypes.POINTER(SolveOpts)]
         L.lddmm_solve.argtypes = [_vp, ctypes.POINTER(Params), ctypes.POINTER(SolveOpts), _vp, _vp,
                                   _vp, ctypes.POINTER(SolveResult), _vp, _vp]
@@ -85,7 +115,9 @@ def lib():
         for f in ("lddmm_ctx_create", "lddmm_ctx_destroy", "lddmm_workspace_size",
                   "lddmm_shoot_forward", "lddmm_shoot_grad", "lddmm_ctx_check",
                   "lddmm_ctx_set_timing", "lddmm_ctx_timing", "lddmm_solve_opts_default",
-                  "lddmm_solve"):
+                  "lddmm_solve", "lddmm_server_create", "lddmm_server_job_footprint",
+                  "lddmm_server_submit", "lddmm_server_poll", "lddmm_server_wait",
+                  "lddmm_server_stats_get", "lddmm_server_destroy"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -254,6 +286,114 @@ class Context:
     def check(self, stream=None) -> int:
         """Synchronise and report a non-finite loss since the last check."""
         return _check(lib().lddmm_ctx_check(self._h, _stream(stream)), self._h)
+
+
+def server_config(T: int, precision="fp32c", max_slots: int = 32, max_n: int = 8192,
+                  hbm_budget_bytes: int = 1 << 30, device: int = 0) -> ServerConfig:
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    return ServerConfig(int(device), int(max_slots), int(max_n), int(T), prec,
+                        int(hbm_budget_bytes))
+
+
+def job_footprint(cfg: ServerConfig, n: int, m: int = 5) -> int:
+    """Device bytes one job occupies in a server (host computation)."""
+    b = ctypes.c_size_t(0)
+    _check(lib().lddmm_server_job_footprint(ctypes.byref(cfg), int(n), int(m), ctypes.byref(b)))
+    return int(b.value)
+
+
+class Server:
+    """Continuous-batching registration server (``lddmm_server``).  Inputs
+    are host float64 [N,3] arrays; results come back as numpy arrays."""
+
+    def __init__(self, T: int, precision="fp32c", max_slots: int = 32, max_n: int = 8192,
+                 hbm_budget_bytes: int = 1 << 30, device: int = 0):
+        self.cfg = server_config(T, precision, max_slots, max_n, hbm_budget_bytes, device)
+        self.precision = precision
+        h = _vp()
+        rc = lib().lddmm_server_create(ctypes.byref(self.cfg), ctypes.byref(h))
+        if rc != OK:
+            raise LddmmError(rc, lib().lddmm_server_last_error(None).decode())
+        self._h = h
+        self._n = {}
+
+    def _err(self, rc):
+        raise LddmmError(rc, lib().lddmm_server_last_error(self._h).decode()
+                         or lib().lddmm_status_string(rc).decode())
+
+    def submit(self, q0, target, sigma: float, lam: float, p0=None, **opts) -> int:
+        import numpy as np
+        q0 = np.ascontiguousarray(q0, dtype=np.float64)
+        target = np.ascontiguousarray(target, dtype=np.float64)
+        n = q0.shape[0]
+        prm = make_params(n, self.cfg.T, sigma, lam, self.cfg.precision)
+        if p0 is not None:
+            opts.setdefault("init", 2)
+            p0 = np.ascontiguousarray(p0, dtype=np.float64)
+        o = solve_opts(self.cfg.precision, **opts)
+        jid = ctypes.c_int64(0)
+        rc = lib().lddmm_server_submit(self._h, ctypes.byref(prm), ctypes.byref(o),
+                                       q0.ctypes.data, target.ctypes.data,
+                                       p0.ctypes.data if p0 is not None else None,
+                                       ctypes.byref(jid))
+        if rc != OK:
+            self._err(rc)
+        self._n[jid.value] = n
+        return jid.value
+
+    def poll(self, job_id: int):
+        """None while the job runs; else dict(p0, status, loss, ..., times)."""
+        import numpy as np
+        n = self._n[job_id]
+        p0 = np.empty((n, 3))
+        res, tm = SolveResult(), JobTimes()
+        rc = lib().lddmm_server_poll(self._h, job_id, p0.ctypes.data, ctypes.byref(res),
+                                     ctypes.byref(tm))
+        if rc == EBUSY:
+            return None
+        if rc not in (OK, ENOTCONV, ENONFINITE):
+            self._err(rc)
+        del self._n[job_id]
+        r = {k: getattr(res, k) for k, _ in SolveResult._fields_}
+        r.update(p0=p0, submit_s=tm.submit_s, admit_s=tm.admit_s, done_s=tm.done_s)
+        return r
+
+    def wait(self, job_id: int, timeout: float | None = None) -> bool:
+        rc = lib().lddmm_server_wait(self._h, job_id, -1.0 if timeout is None else float(timeout))
+        if rc == EBUSY:
+            return False
+        if rc != OK:
+            self._err(rc)
+        return True
+
+    def result(self, job_id: int, timeout: float | None = None):
+        if not self.wait(job_id, timeout):
+            raise TimeoutError(f"job {job_id} not done")
+        return self.poll(job_id)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        rc = lib().lddmm_server_stats_get(self._h, ctypes.byref(st))
+        if rc != OK:
+            self._err(rc)
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().lddmm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def version() -> str:

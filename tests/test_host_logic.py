@@ -1,0 +1,42 @@
+"""Host-side logic that needs no GPU: the serving arena, job footprints and
+the automatic checkpoint choice."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_arena_allocator(tmp_path):
+    exe = tmp_path / "arena_test"
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-fsanitize=address,undefined",
+                    "-I", os.path.join(ROOT, "paper_1907_04839_amd", "csrc"),
+                    os.path.join(ROOT, "tests", "cpp", "arena_test.cpp"), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert "arena ok" in out.stdout
+
+
+def test_job_footprint_grows_with_n_and_T():
+    import torch  # noqa: F401
+    from paper_1907_04839_amd import lddmm
+    cfg = lddmm.server_config(40, "fp32c")
+    a = lddmm.job_footprint(cfg, 500)
+    b = lddmm.job_footprint(cfg, 8000)
+    assert 0 < a < b
+    # trajectory of (T+1) 32-byte records dominates: ~ (T+1) * 32 * N
+    assert b > 41 * 32 * 8000
+    cfg64 = lddmm.server_config(40, "fp64")
+    assert lddmm.job_footprint(cfg64, 8000) > b
+    with pytest.raises(lddmm.LddmmError):
+        lddmm.job_footprint(cfg, 0)
+
+
+def test_auto_checkpoint_choice():
+    from paper_1907_04839_amd.autograd import ShootConfig
+    assert ShootConfig(100, 6.0, 1.0, "fp32c", "auto", 1 << 30).resolve_ckpt(16384) == 0
+    s = ShootConfig(100, 6.0, 1.0, "fp32c", "auto", 8 << 20).resolve_ckpt(16384)
+    assert 1 <= s <= 10 and (s + 1) * 16384 * 32 <= 8 << 20
+    assert ShootConfig(100, 6.0, 1.0, "fp32c", 7).resolve_ckpt(16384) == 7
