@@ -60,13 +60,18 @@ struct AccOf { using type = double; };
 template <typename R>
 struct Rec;
 
-// Field-wise copy of record j (an address-space-qualified struct cannot be
-// copied as a whole); adjacent scalar loads merge into one wide load.
+// Record j as one 8-wide vector load (an address-space-qualified struct
+// cannot be copied as a whole): a wave-uniform j gives one s_load_dwordx8
+// (FP32) or s_load_dwordx16 (FP64) that the compiler issues ahead of use.
+template <typename R>
+using Vec8 = R __attribute__((ext_vector_type(8)));
+
 template <typename R>
 __device__ __forceinline__ Rec<R> load_rec(GlobalPtr<Rec<R>> p, int j) {
+  const Vec8<R> v = *reinterpret_cast<GlobalPtr<Vec8<R>>>(p + j);
   Rec<R> r;
-  r.x = p[j].x; r.y = p[j].y; r.z = p[j].z; r.u = p[j].u;
-  r.px = p[j].px; r.py = p[j].py; r.pz = p[j].pz; r.w = p[j].w;
+  r.x = v[0]; r.y = v[1]; r.z = v[2]; r.u = v[3];
+  r.px = v[4]; r.py = v[5]; r.pz = v[6]; r.w = v[7];
   return r;
 }
 template <>

@@ -1,0 +1,40 @@
+"""Precision study on the 65536-landmark two-blob workload: one gradient in
+FP32 (one running sum per wave), FP32 compensated (64-pair tiles folded into
+FP64) and FP64, each against the FP64 oracle on the full problem.
+
+The oracle's full-T evaluation costs ~4e11 pair terms (minutes on 16 host
+threads), so by default the study runs the full N with T = 5 Euler steps;
+LDDMM_PRECISION_STUDY_T=50 runs the workload's own T."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1907_04839_amd import synth
+
+from conftest import rel_err, to_dev
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def test_precision_modes_against_oracle(gpu_ctx, orc_mt):
+    import torch
+    pb = synth.two_blobs()
+    T = int(os.environ.get("LDDMM_PRECISION_STUDY_T", "5"))
+    o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, T)
+    errs = {}
+    for mode in ("fp32", "fp32c", "fp64"):
+        r = gpu_ctx.shoot_grad(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), T, pb.sigma,
+                               pb.lam, precision=mode)
+        torch.cuda.synchronize()
+        errs[mode] = dict(loss=abs(r.loss.item() - o["loss"]) / abs(o["loss"]),
+                          H0=abs(r.H0.item() - o["H0"]) / abs(o["H0"]),
+                          q1=rel_err(r.q1.cpu().numpy(), o["q1"]),
+                          grad=rel_err(r.grad.cpu().numpy(), o["grad"]))
+        print(f"[precision blobs65536 T={T} {mode}] " +
+              " ".join(f"{k}={v:.2e}" for k, v in errs[mode].items()), flush=True)
+    assert max(errs["fp64"].values()) <= 1e-12
+    assert max(errs["fp32c"].values()) <= 1e-5
+    # one running FP32 sum over 4096 pairs per wave: expected to lose accuracy with N
+    assert max(errs["fp32"].values()) <= 1e-4
+    assert errs["fp32c"]["grad"] <= errs["fp32"]["grad"]
