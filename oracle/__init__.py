@@ -61,6 +61,10 @@ def lib():
         L.oracle_shoot_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                         _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
         L.oracle_shoot_grad.restype = ctypes.c_int
+        L.oracle_shoot_grad_all.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                            ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                            _dp, _dp, ctypes.c_int]
+        L.oracle_shoot_grad_all.restype = ctypes.c_int
         L.oracle_solve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    _dp, _dp, _dp, ctypes.POINTER(_Opts), ctypes.POINTER(_Result),
                                    _dp, ctypes.c_int]
@@ -155,21 +159,28 @@ def shoot_forward(q0, p0, sigma: float, T: int, traj: bool = False, compensated:
     return out
 
 
-def shoot_grad(q0, p0, x, sigma: float, lam: float, T: int, compensated: bool = False):
+def shoot_grad(q0, p0, x, sigma: float, lam: float, T: int, compensated: bool = False,
+               all_grads: bool = False):
     """Loss L = H(q0,p0) + lam |q(1)-x|^2 (eq. 3) and dL/dp0 (exact discrete adjoint).
 
-    Returns dict(loss, grad, q1, H0, mismatch).
+    Returns dict(loss, grad, q1, H0, mismatch[, grad_q0, grad_x]).
     """
     q0, p0, x = _in(q0), _in(p0), _in(x)
     n = q0.shape[0]
     grad, q1 = np.empty_like(q0), np.empty_like(q0)
+    gq = np.empty_like(q0) if all_grads else None
+    gx = np.empty_like(q0) if all_grads else None
     loss = ctypes.c_double(0.0)
     terms = np.zeros(2)
-    rc = lib().oracle_shoot_grad(n, int(T), float(sigma), float(lam), _p(q0), _p(p0), _p(x),
-                                 ctypes.byref(loss), _p(grad), _p(q1), _p(terms), int(compensated))
+    rc = lib().oracle_shoot_grad_all(n, int(T), float(sigma), float(lam), _p(q0), _p(p0), _p(x),
+                                     ctypes.byref(loss), _p(grad), _p(gq), _p(gx), _p(q1),
+                                     _p(terms), int(compensated))
     if rc != 0:
         raise MemoryError("oracle_shoot_grad")
-    return dict(loss=loss.value, grad=grad, q1=q1, H0=float(terms[0]), mismatch=float(terms[1]))
+    out = dict(loss=loss.value, grad=grad, q1=q1, H0=float(terms[0]), mismatch=float(terms[1]))
+    if all_grads:
+        out.update(grad_q0=gq, grad_x=gx)
+    return out
 
 
 @dataclass

@@ -17,7 +17,8 @@
  *               from the step-t values (Alg. 1, forward loop)
  *   objective   L(p0) = H(q0,p0) + lambda sum_i |q_i(1) - x_i|^2   (eq. 3)
  *   gradient    exact adjoint of the discrete Euler map, run backwards in
- *               time (Alg. 1, backward loop); dL/dp0 = b(0) + Hp(q0,p0)
+ *               time (Alg. 1, backward loop); dL/dp0 = b(0) + Hp(q0,p0),
+ *               and also dL/dq0 = a(0) + Hq(q0,p0), dL/dx = -2 lambda (q(1)-x)
  *   optimiser   L-BFGS on p0 (Sec. 2.1 and Alg. 1, steps (e)-(f)), own
  *               implementation: two-loop recursion + strong-Wolfe search
  *
@@ -248,9 +249,9 @@ void oracle_pair_adjoint_rows(int n, double sigma, const double *q, const double
 
 /* traj (optional): (T+1) slots of [q (3N), p (3N)]; slot t = state at step t.
  * Hp0 (optional): Hp(q0,p0), 3N.  Returns 0, or -2 when memory runs out. */
-int oracle_shoot_forward(int n, int T, double sigma, const double *q0, const double *p0,
-                         double *q1, double *p1, double *H0, double *traj, double *Hp0,
-                         int compensated) {
+static int shoot_forward_impl(int n, int T, double sigma, const double *q0, const double *p0,
+                              double *q1, double *p1, double *H0, double *traj, double *Hp0,
+                              double *Hq0, int compensated) {
     size_t m = 3 * (size_t)n;
     double *q = (double *)malloc(sizeof(double) * m), *p = (double *)malloc(sizeof(double) * m);
     double *Hq = (double *)malloc(sizeof(double) * m), *Hp = (double *)malloc(sizeof(double) * m);
@@ -266,6 +267,7 @@ int oracle_shoot_forward(int n, int T, double sigma, const double *q0, const dou
         oracle_pair_forward(n, sigma, q, p, Hq, Hp, compensated);
         if (t == 0) {
             if (Hp0) memcpy(Hp0, Hp, sizeof(double) * m);
+            if (Hq0) memcpy(Hq0, Hq, sizeof(double) * m);
             if (H0) {   /* H(q0,p0) = 1/2 sum_i p0_i . Hp_i(q0,p0) */
                 acc_t h = {0, 0};
                 for (size_t k = 0; k < m; ++k) acc_add(&h, p[k] * Hp[k], compensated);
@@ -287,25 +289,35 @@ int oracle_shoot_forward(int n, int T, double sigma, const double *q0, const dou
     return 0;
 }
 
+int oracle_shoot_forward(int n, int T, double sigma, const double *q0, const double *p0,
+                         double *q1, double *p1, double *H0, double *traj, double *Hp0,
+                         int compensated) {
+    return shoot_forward_impl(n, T, sigma, q0, p0, q1, p1, H0, traj, Hp0, NULL, compensated);
+}
+
 /* ------------------------------------------------------------------------ */
 /* loss and gradient (Alg. 1 ComputeGradient, eq. 3)                        */
 /* ------------------------------------------------------------------------ */
 
-/* terms (optional): [H0, mismatch sum |q1-x|^2].  q1 (optional): q(1). */
-int oracle_shoot_grad(int n, int T, double sigma, double lambda, const double *q0,
-                      const double *p0, const double *x, double *loss, double *grad,
-                      double *q1, double *terms, int compensated) {
+/* Loss and its gradients.  terms (optional): [H0, mismatch sum |q1-x|^2];
+ * q1 (optional): q(1).  grad_q0, grad_x (optional): dL/dq0 = a(0) + Hq(q0,p0)
+ * (the adjoint of q at t = 0 plus the energy term's own dependence on q0)
+ * and dL/dx = -2 lambda (q(1) - x). */
+int oracle_shoot_grad_all(int n, int T, double sigma, double lambda, const double *q0,
+                          const double *p0, const double *x, double *loss, double *grad,
+                          double *grad_q0, double *grad_x, double *q1, double *terms,
+                          int compensated) {
     size_t m = 3 * (size_t)n;
     double *traj = (double *)malloc(sizeof(double) * (size_t)(T + 1) * 2 * m);
-    double *Hp0 = (double *)malloc(sizeof(double) * m);
+    double *Hp0 = (double *)malloc(sizeof(double) * m), *Hq0 = (double *)malloc(sizeof(double) * m);
     double *a = (double *)malloc(sizeof(double) * m), *b = (double *)malloc(sizeof(double) * m);
     double *A = (double *)malloc(sizeof(double) * m), *B = (double *)malloc(sizeof(double) * m);
-    if (!traj || !Hp0 || !a || !b || !A || !B) {
-        free(traj); free(Hp0); free(a); free(b); free(A); free(B);
+    if (!traj || !Hp0 || !Hq0 || !a || !b || !A || !B) {
+        free(traj); free(Hp0); free(Hq0); free(a); free(b); free(A); free(B);
         return -2;
     }
     double H0 = 0.0;
-    oracle_shoot_forward(n, T, sigma, q0, p0, NULL, NULL, &H0, traj, Hp0, compensated);
+    shoot_forward_impl(n, T, sigma, q0, p0, NULL, NULL, &H0, traj, Hp0, Hq0, compensated);
     const double *qT = traj + (size_t)T * 2 * m;
     acc_t mis = {0, 0};
     for (size_t k = 0; k < m; ++k) {
@@ -313,6 +325,7 @@ int oracle_shoot_grad(int n, int T, double sigma, double lambda, const double *q
         acc_add(&mis, r * r, compensated);
         a[k] = 2.0 * lambda * r;    /* dL/dq(1) */
         b[k] = 0.0;                 /* dL/dp(1) */
+        if (grad_x) grad_x[k] = -2.0 * lambda * r;
     }
     double mismatch = acc_get(&mis);
     if (loss) *loss = H0 + lambda * mismatch;
@@ -329,8 +342,17 @@ int oracle_shoot_grad(int n, int T, double sigma, double lambda, const double *q
     }
     if (grad)
         for (size_t k = 0; k < m; ++k) grad[k] = b[k] + Hp0[k];
-    free(traj); free(Hp0); free(a); free(b); free(A); free(B);
+    if (grad_q0)
+        for (size_t k = 0; k < m; ++k) grad_q0[k] = a[k] + Hq0[k];
+    free(traj); free(Hp0); free(Hq0); free(a); free(b); free(A); free(B);
     return 0;
+}
+
+int oracle_shoot_grad(int n, int T, double sigma, double lambda, const double *q0,
+                      const double *p0, const double *x, double *loss, double *grad,
+                      double *q1, double *terms, int compensated) {
+    return oracle_shoot_grad_all(n, T, sigma, lambda, q0, p0, x, loss, grad, NULL, NULL, q1,
+                                 terms, compensated);
 }
 
 /* ------------------------------------------------------------------------ */

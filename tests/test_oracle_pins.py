@@ -367,3 +367,56 @@ def test_solve_trace_is_monotone(orc):
     assert np.all(np.diff(f) <= 0.0)
     assert r["iters"] == 15 or r["status"] == 0
     assert r["fevals"] >= r["iters"] + 1
+
+
+# ---------------------------------------------------------------- gradients w.r.t. q0 and x
+
+def test_gradients_wrt_q0_and_target_match_central_differences(orc):
+    q0, p0, rng = rand(91, 6, spread=1.5, p_scale=0.8)
+    x = q0 + rng.standard_normal(q0.shape)
+    sigma, lam, T, eps = 1.3, 1.7, 5, 1e-6
+    r = orc.shoot_grad(q0, p0, x, sigma, lam, T, all_grads=True)
+    fq, fx = np.zeros_like(q0), np.zeros_like(q0)
+    for i in range(q0.shape[0]):
+        for d in range(3):
+            for arr, out, which in ((q0, fq, "q"), (x, fx, "x")):
+                ap, am = arr.copy(), arr.copy()
+                ap[i, d] += eps
+                am[i, d] -= eps
+                if which == "q":
+                    lp = orc.shoot_grad(ap, p0, x, sigma, lam, T)["loss"]
+                    lm = orc.shoot_grad(am, p0, x, sigma, lam, T)["loss"]
+                else:
+                    lp = orc.shoot_grad(q0, p0, ap, sigma, lam, T)["loss"]
+                    lm = orc.shoot_grad(q0, p0, am, sigma, lam, T)["loss"]
+                out[i, d] = (lp - lm) / (2 * eps)
+    assert rel(r["grad_q0"], fq) < 2e-8
+    assert rel(r["grad_x"], fx) < 1e-9
+    # the energy term alone: with lam = 0, dL/dq0 = Hq(q0, p0) and dL/dx = 0
+    r0 = orc.shoot_grad(q0, p0, x, sigma, 0.0, T, all_grads=True)
+    np.testing.assert_allclose(r0["grad_q0"], orc.pair_forward(q0, p0, sigma)[0], atol=1e-14)
+    assert np.all(r0["grad_x"] == 0.0)
+
+
+def test_translation_identity_of_the_gradients(orc):
+    """L(q0 + tau, x + tau) = L(q0, x) for every tau, so the q0- and
+    x-gradients sum to zero over all landmarks."""
+    q0, p0, rng = rand(92, 40)
+    x = q0 + rng.standard_normal(q0.shape)
+    r = orc.shoot_grad(q0, p0, x, 1.4, 2.0, 7, all_grads=True)
+    total = r["grad_q0"].sum(0) + r["grad_x"].sum(0)
+    assert np.abs(total).max() < 1e-10 * np.abs(r["grad_q0"]).sum()
+
+
+def test_gradient_wrt_q0_matches_dense_autograd_model(orc):
+    import torch
+    q0, p0, rng = rand(93, 15, spread=1.5, p_scale=0.6)
+    x = q0 + rng.standard_normal(q0.shape)
+    sigma, lam, T = 1.1, 1.7, 4
+    tq = torch.tensor(q0, dtype=torch.float64, requires_grad=True)
+    tp = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    tx = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    gq, gx = torch.autograd.grad(_torch_loss(tq, tp, tx, sigma, lam, T), (tq, tx))
+    r = orc.shoot_grad(q0, p0, x, sigma, lam, T, all_grads=True)
+    assert rel(r["grad_q0"], gq.numpy()) < 1e-12
+    assert rel(r["grad_x"], gx.numpy()) < 1e-13
