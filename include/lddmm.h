@@ -222,6 +222,17 @@ const char* lddmm_server_last_error(lddmm_server* srv);
  * jobs and frees everything.  NULL is accepted. */
 lddmm_status lddmm_server_destroy(lddmm_server* srv);
 
+/* Loss and all its gradients: as lddmm_shoot_grad, plus (each optional)
+ *   grad_q0 : out, [n][3] device FP64, dL/dq0 = a(0) + Hq(q0,p0): the adjoint
+ *             of q at t = 0 plus the energy term's own dependence on q0
+ *   grad_x  : out, [n][3] device FP64, dL/dx = -2 lambda (q(1) - x)
+ * (eq. 3 differentiated through the discrete flow; with them the template
+ * and the target can be optimised too).  Errors: EINVAL, ENOMEM, EDEVICE. */
+lddmm_status lddmm_shoot_grad_all(lddmm_ctx* ctx, const lddmm_params* params, const double* q0,
+                                  const double* p0, const double* target, double* out3,
+                                  double* grad_p0, double* grad_q0, double* grad_x, double* q1,
+                                  void* stream);
+
 /* Waits for the context's work on `stream` and reports whether any call
  * since the last check produced a non-finite loss (then ENONFINITE, and the
  * flag is cleared).  Errors: EINVAL, EDEVICE. */

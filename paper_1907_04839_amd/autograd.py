@@ -4,8 +4,9 @@ adjoint gradient.
 ``ShootLoss.apply(p0, q0, target, cfg)`` returns the scalar FP64 loss
 L(p0) = H(q0, p0) + lambda |q(1) - x|^2.  Its forward pass runs one
 ``lddmm_shoot_grad`` (forward flow, loss and adjoint pass in the HIP
-library), so the gradient is ready when the loss is; backward only scales
-it.  Gradients flow to p0 only.
+library), so the gradients are ready when the loss is; backward only scales
+them.  Gradients flow to p0, and to q0 and the target when they require
+them (``lddmm_shoot_grad_all``).
 
 When the whole trajectory (T+1 records of N landmarks) would not fit in the
 configured budget, the library keeps every s-th FP64 state and recomputes
@@ -60,20 +61,27 @@ class ShootLoss(torch.autograd.Function):
                 cfg: ShootConfig):
         n = q0.shape[0]
         ctx = context(q0.device.index)
+        want_q0, want_x = actx.needs_input_grad[1], actx.needs_input_grad[2]
         r = ctx.shoot_grad(q0.detach().contiguous(), p0.detach().contiguous(),
                            target.detach().contiguous(), cfg.T, cfg.sigma, cfg.lam,
                            precision=cfg.precision, ckpt_every=cfg.resolve_ckpt(n),
-                           want_q1=False)
-        actx.save_for_backward(r.grad)
+                           want_q1=False, want_grad_q0=want_q0, want_grad_x=want_x)
+        saved = [r.grad] + ([r.grad_q0] if want_q0 else []) + ([r.grad_x] if want_x else [])
+        actx.save_for_backward(*saved)
+        actx.layout = (want_q0, want_x)
         return r.loss.clone()
 
     @staticmethod
     def backward(actx, grad_out: torch.Tensor):
-        (g,) = actx.saved_tensors
-        return grad_out * g, None, None, None
+        saved = list(actx.saved_tensors)
+        want_q0, want_x = actx.layout
+        g = saved.pop(0)
+        gq = grad_out * saved.pop(0) if want_q0 else None
+        gx = grad_out * saved.pop(0) if want_x else None
+        return grad_out * g, gq, gx, None
 
 
 def shoot_loss(p0, q0, target, T: int, sigma: float, lam: float, precision: str = "fp32c",
                ckpt_every: int | str = "auto") -> torch.Tensor:
-    """Differentiable loss of eq. 3 with respect to p0."""
+    """Differentiable loss of eq. 3 (with respect to p0, q0 and target)."""
     return ShootLoss.apply(p0, q0, target, ShootConfig(T, sigma, lam, precision, ckpt_every))

@@ -137,7 +137,7 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Byte offsets of the workspace buffers of one problem.
 struct Layout {
-  size_t st, ad, hp0, xc, cen, h0p, out3, traj, arec, ckpt, partial, total;
+  size_t st, ad, hp0, hq0, xc, cen, h0p, out3, traj, arec, ckpt, partial, total;
   int slots;   // trajectory slots
   int nseg;    // checkpoint segments (0 = full trajectory)
 };
@@ -150,6 +150,7 @@ Layout make_layout(const lddmm_params& p, const Plan& plan) {
   L.st = take(6 * n * 8);
   L.ad = take(6 * n * 8);
   L.hp0 = take(3 * n * 8);
+  L.hq0 = take(3 * n * 8);
   L.xc = take(3 * n * 8);
   L.cen = take(4 * 8);
   L.h0p = take((size_t)plan.nb * 8);
@@ -195,7 +196,7 @@ struct Job {
   Scales sc;
   Layout L;
   void* ws;
-  double *st, *ad, *hp0, *xc, *cen, *h0p, *out3, *ckpt;
+  double *st, *ad, *hp0, *hq0, *xc, *cen, *h0p, *out3, *ckpt;
   char *traj, *arec;
   void* partial;
   size_t rb;
@@ -218,6 +219,7 @@ Job make_job(const lddmm_params& p, void* ws) {
   j.st = at<double>(ws, j.L.st);
   j.ad = at<double>(ws, j.L.ad);
   j.hp0 = at<double>(ws, j.L.hp0);
+  j.hq0 = at<double>(ws, j.L.hq0);
   j.xc = at<double>(ws, j.L.xc);
   j.cen = at<double>(ws, j.L.cen);
   j.h0p = at<double>(ws, j.L.h0p);
@@ -232,7 +234,7 @@ Job make_job(const lddmm_params& p, void* ws) {
 
 // Forward Euler steps t in [t0, t1).  first: capture Hp(q0,p0) and H0 at t == 0.
 hipError_t run_forward(const Job& j, int t0, int t1, bool first, bool store_ckpt, hipStream_t s,
-                       Timer* tm) {
+                       Timer* tm, bool want_hq0 = false) {
   const int mode = j.p.precision;
   for (int t = t0; t < t1; ++t) {
     FwdArgs a{};
@@ -242,6 +244,7 @@ hipError_t run_forward(const Job& j, int t0, int t1, bool first, bool store_ckpt
     a.rec_t1 = j.slot(t + 1);
     a.st = j.st;
     a.hp0 = (first && t == 0) ? j.hp0 : nullptr;
+    a.hq0 = (first && t == 0 && want_hq0) ? j.hq0 : nullptr;
     a.h0_part = (first && t == 0) ? j.h0p : nullptr;
     const int s_every = j.p.ckpt_every;
     a.ckpt = (store_ckpt && j.L.nseg > 0 && (t + 1) % s_every == 0 && t + 1 < j.p.T)
@@ -255,7 +258,7 @@ hipError_t run_forward(const Job& j, int t0, int t1, bool first, bool store_ckpt
 
 // Adjoint steps t = t1-1 down to t0; *cur is the adjoint record buffer in use.
 hipError_t run_adjoint(const Job& j, int t0, int t1, int* cur, double* grad, hipStream_t s,
-                       Timer* tm) {
+                       Timer* tm, double* grad_q0 = nullptr) {
   const int mode = j.p.precision;
   for (int t = t1 - 1; t >= t0; --t) {
     AdjArgs a{};
@@ -267,6 +270,8 @@ hipError_t run_adjoint(const Job& j, int t0, int t1, int* cur, double* grad, hip
     a.ad = j.ad;
     a.hp0 = j.hp0;
     a.grad = t == 0 ? grad : nullptr;
+    a.hq0 = j.hq0;
+    a.grad_q0 = t == 0 ? grad_q0 : nullptr;
     a.partial = j.partial;
     hipError_t e = launch_adj_step(mode, j.plan, a, s, tm->take(1));
     if (e != hipSuccess) return e;
@@ -291,7 +296,7 @@ lddmm_status begin(lddmm_ctx* ctx, const lddmm_params* params, Job* job) {
 // One loss+gradient evaluation (Alg. 1 ComputeGradient) of a prepared job.
 lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const double* p0,
                       const double* target, double* out3, double* grad, double* q1,
-                      hipStream_t s) {
+                      hipStream_t s, double* grad_q0 = nullptr, double* grad_x = nullptr) {
   const lddmm_params* params = &j.p;
   const int n = params->n, T = params->T, mode = params->precision;
   HIP_TRY(ctx, launch_centroid(q0, n, j.cen, s), "centroid");
@@ -300,13 +305,14 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
   if (j.L.nseg > 0)
     HIP_TRY(ctx, hipMemcpyAsync(j.ckpt_state(0), j.st, 6 * (size_t)n * 8, hipMemcpyDeviceToDevice, s),
             "checkpoint 0");
-  HIP_TRY(ctx, run_forward(j, 0, T, true, true, s, &ctx->timer), "forward step");
+  HIP_TRY(ctx, run_forward(j, 0, T, true, true, s, &ctx->timer, grad_q0 != nullptr),
+          "forward step");
   HIP_TRY(ctx, launch_loss(mode, n, j.plan.nb, params->lambda, j.sc.bscale, j.st, j.xc, j.cen,
-                           j.h0p, j.ad, j.arec_buf(0), out3, q1, nullptr, ctx->flag, s),
+                           j.h0p, j.ad, j.arec_buf(0), out3, q1, nullptr, ctx->flag, grad_x, s),
           "loss");
   int cur = 0;
   if (j.L.nseg == 0) {
-    HIP_TRY(ctx, run_adjoint(j, 0, T, &cur, grad, s, &ctx->timer), "adjoint step");
+    HIP_TRY(ctx, run_adjoint(j, 0, T, &cur, grad, s, &ctx->timer, grad_q0), "adjoint step");
   } else {
     const int every = params->ckpt_every;
     for (int seg = j.L.nseg - 1; seg >= 0; --seg) {
@@ -316,7 +322,7 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
                 "restore");
         HIP_TRY(ctx, run_forward(j, t0, t1, false, false, s, &ctx->timer), "recompute step");
       }
-      HIP_TRY(ctx, run_adjoint(j, t0, t1, &cur, grad, s, &ctx->timer), "adjoint step");
+      HIP_TRY(ctx, run_adjoint(j, t0, t1, &cur, grad, s, &ctx->timer, grad_q0), "adjoint step");
     }
   }
   return LDDMM_OK;
@@ -418,6 +424,19 @@ lddmm_status lddmm_shoot_grad(lddmm_ctx* ctx, const lddmm_params* params, const 
   lddmm_status st = begin(ctx, params, &j);
   if (st != LDDMM_OK) return st;
   return run_grad(ctx, j, q0, p0, target, out3, grad, q1, static_cast<hipStream_t>(stream));
+}
+
+lddmm_status lddmm_shoot_grad_all(lddmm_ctx* ctx, const lddmm_params* params, const double* q0,
+                                  const double* p0, const double* target, double* out3,
+                                  double* grad_p0, double* grad_q0, double* grad_x, double* q1,
+                                  void* stream) {
+  if (ctx && (!q0 || !p0 || !target || !out3 || !grad_p0))
+    return fail(ctx, LDDMM_EINVAL, "q0, p0, target, out3 and grad_p0 must not be NULL");
+  Job j;
+  lddmm_status st = begin(ctx, params, &j);
+  if (st != LDDMM_OK) return st;
+  return run_grad(ctx, j, q0, p0, target, out3, grad_p0, q1, static_cast<hipStream_t>(stream),
+                  grad_q0, grad_x);
 }
 
 lddmm_status lddmm_solve_opts_default(int32_t precision, lddmm_solve_opts* o) {

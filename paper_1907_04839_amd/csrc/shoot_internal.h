@@ -48,6 +48,7 @@ struct FwdArgs {
   void* rec_t1;         // point records at step t+1 (written)
   double* st;           // FP64 state [6][n]: q (3 rows) then p (3 rows), centred
   double* hp0;          // [3][n]: Hp(q0,p0) (written at t == 0, else null)
+  double* hq0;          // [3][n]: Hq(q0,p0) (optional, with hp0)
   double* h0_part;      // [nb]: per i-block sum p0.Hp0 (t == 0, else null)
   double* ckpt;         // [6][n]: copy of the new state (null unless a checkpoint)
   void* partial;        // [S][6][n] partial sums when S > 1
@@ -63,6 +64,8 @@ struct AdjArgs {
   double* ad;           // FP64 adjoint state [6][n]: a (3 rows) then b (3 rows)
   const double* hp0;    // [3][n] Hp(q0,p0)
   double* grad;         // [n][3] gradient, written at t == 0 (else null)
+  const double* hq0;    // [3][n] Hq(q0,p0), with grad_q0
+  double* grad_q0;      // [n][3] dL/dq0 = a(0) + Hq(q0,p0), at t == 0 (optional)
   void* partial;        // [S][9][n] partial sums when S > 1
 };
 
@@ -83,10 +86,11 @@ hipError_t launch_adj_step(int mode, const Plan& p, const AdjArgs& a, hipStream_
                            hipEvent_t* ev = nullptr);
 // Loss and terminal adjoint: L = H0 + lambda |q(1) - x|^2, a = 2 lambda (q(1) - x), b = 0.
 // out3 = {loss, H0, mismatch}; q1/p1 (optional) receive the final state, uncentred, [n][3].
+// grad_x (optional): dL/dx = -2 lambda (q(1) - x), [n][3].
 hipError_t launch_loss(int mode, int n, int nb, double lambda, double bscale, const double* st,
                        const double* xc, const double* cen, const double* h0_part, double* ad,
                        void* arec0, double* out3, double* q1, double* p1, int* flag,
-                       hipStream_t s);
+                       double* grad_x, hipStream_t s);
 // Forward-only epilogue: writes H0 (device scalar) and the final state.
 hipError_t launch_forward_out(int n, int nb, const double* st, const double* cen,
                               const double* h0_part, double* H0, double* q1, double* p1,

@@ -219,7 +219,7 @@ __device__ __forceinline__ void block_combine(Acc* red, const Acc o[NC], int w, 
 // FP64 state of one landmark, loaded before the sums it is combined with so
 // that its memory latency overlaps them.
 struct FwdState { double q[3], p[3]; };
-struct AdjState { double a[3], b[3], hp0[3]; };
+struct AdjState { double a[3], b[3], hp0[3], hq0[3]; };
 
 __device__ __forceinline__ FwdState load_fwd_state(const FwdArgs& A, int i) {
   FwdState v;
@@ -235,6 +235,7 @@ __device__ __forceinline__ AdjState load_adj_state(const AdjArgs& A, int i) {
     v.a[c] = A.ad[c * A.n + ic];
     v.b[c] = A.ad[(3 + c) * A.n + ic];
     v.hp0[c] = A.grad ? A.hp0[c * A.n + ic] : 0.0;
+    v.hq0[c] = A.grad_q0 ? A.hq0[c * A.n + ic] : 0.0;
   }
   return v;
 }
@@ -252,6 +253,7 @@ __device__ __forceinline__ void fwd_finish(const FwdArgs& A, int ib, int lane, F
     }
     for (int c = 0; c < 3; ++c) {
       const double hq = A.sc.hq * hqs[c];
+      if (A.hq0) A.hq0[c * n + i] = hq;
       v.q[c] = v.q[c] + A.sc.dt * hp[c];
       v.p[c] = v.p[c] - A.sc.dt * hq;
     }
@@ -286,6 +288,8 @@ __device__ __forceinline__ void adj_finish(const AdjArgs& A, int ib, int lane, A
       make_rec<R>(v.a[0], v.a[1], v.a[2], bs * v.b[0], bs * v.b[1], bs * v.b[2]);
   if (A.grad)
     for (int c = 0; c < 3; ++c) A.grad[3 * i + c] = v.b[c] + v.hp0[c];
+  if (A.grad_q0)
+    for (int c = 0; c < 3; ++c) A.grad_q0[3 * i + c] = v.a[c] + v.hq0[c];
 }
 
 // ---------------------------------------------------------------------------
@@ -507,7 +511,7 @@ __device__ __forceinline__ void loss_body(int n, int nb, double lambda, const do
                                           double* __restrict__ ad, Rec<R>* __restrict__ arec0,
                                           double* __restrict__ out3, double* __restrict__ q1,
                                           double* __restrict__ p1, int* __restrict__ flag,
-                                          double* red) {
+                                          double* __restrict__ grad_x, double* red) {
   double mis = 0.0;
   for (int i = threadIdx.x; i < n; i += kLossThreads) {
     double a[3];
@@ -520,6 +524,7 @@ __device__ __forceinline__ void loss_body(int n, int nb, double lambda, const do
       ad[(3 + c) * n + i] = 0.0;         // dL/dp(1)
       if (q1) q1[3 * i + c] = q + cen[c];
       if (p1) p1[3 * i + c] = st[(3 + c) * n + i];
+      if (grad_x) grad_x[3 * i + c] = -a[c];
     }
     arec0[i] = make_rec<R>(a[0], a[1], a[2], 0.0, 0.0, 0.0);   // b = 0, so b_hat = 0
   }
@@ -539,9 +544,9 @@ __global__ __launch_bounds__(kLossThreads) void k_loss(
     int n, int nb, double lambda, const double* __restrict__ st, const double* __restrict__ xc,
     const double* __restrict__ cen, const double* __restrict__ h0_part, double* __restrict__ ad,
     Rec<R>* __restrict__ arec0, double* __restrict__ out3, double* __restrict__ q1,
-    double* __restrict__ p1, int* __restrict__ flag) {
+    double* __restrict__ p1, int* __restrict__ flag, double* __restrict__ grad_x) {
   __shared__ double red[kLossThreads];
-  loss_body<R>(n, nb, lambda, st, xc, cen, h0_part, ad, arec0, out3, q1, p1, flag, red);
+  loss_body<R>(n, nb, lambda, st, xc, cen, h0_part, ad, arec0, out3, q1, p1, flag, grad_x, red);
 }
 
 __global__ __launch_bounds__(kLossThreads) void k_forward_out(
@@ -636,7 +641,7 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_batch(const BatchJob* __r
   const BatchJob& b = J[blockIdx.x];
   if (!job_live(b)) return;
   loss_body<R>(b.n, b.nb, b.lambda, b.st, b.xc, b.cen, b.h0p, b.ad, static_cast<Rec<R>*>(b.arec),
-               b.out3, b.q1, nullptr, b.flag, red);
+               b.out3, b.q1, nullptr, b.flag, nullptr, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -782,14 +787,16 @@ hipError_t launch_adj_step(int mode, const Plan& p, const AdjArgs& a, hipStream_
 hipError_t launch_loss(int mode, int n, int nb, double lambda, double bscale, const double* st,
                        const double* xc, const double* cen, const double* h0_part, double* ad,
                        void* arec0, double* out3, double* q1, double* p1, int* flag,
-                       hipStream_t s) {
+                       double* grad_x, hipStream_t s) {
   (void)bscale;   // the terminal b is 0, so its scaled record is 0 too
   if (mode == kFP64)
     k_loss<double><<<1, kLossThreads, 0, s>>>(n, nb, lambda, st, xc, cen, h0_part, ad,
-                                              static_cast<Rec<double>*>(arec0), out3, q1, p1, flag);
+                                              static_cast<Rec<double>*>(arec0), out3, q1, p1, flag,
+                                              grad_x);
   else
     k_loss<float><<<1, kLossThreads, 0, s>>>(n, nb, lambda, st, xc, cen, h0_part, ad,
-                                             static_cast<Rec<float>*>(arec0), out3, q1, p1, flag);
+                                             static_cast<Rec<float>*>(arec0), out3, q1, p1, flag,
+                                             grad_x);
   return hipGetLastError();
 }
 

@@ -89,6 +89,8 @@ def lib():
         L.lddmm_workspace_size.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
         L.lddmm_shoot_forward.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp]
         L.lddmm_shoot_grad.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.lddmm_shoot_grad_all.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp,
+                                           _vp, _vp, _vp]
         L.lddmm_ctx_check.argtypes = [_vp, _vp]
         L.lddmm_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]
         L.lddmm_server_job_footprint.argtypes = [ctypes.POINTER(ServerConfig), ctypes.c_int32,
@@ -113,7 +115,8 @@ def lib():
         L.lddmm_last_error.restype = ctypes.c_char_p
         L.lddmm_version.restype = ctypes.c_char_p
         for f in ("lddmm_ctx_create", "lddmm_ctx_destroy", "lddmm_workspace_size",
-                  "lddmm_shoot_forward", "lddmm_shoot_grad", "lddmm_ctx_check",
+                  "lddmm_shoot_forward", "lddmm_shoot_grad", "lddmm_shoot_grad_all",
+                  "lddmm_ctx_check",
                   "lddmm_ctx_set_timing", "lddmm_ctx_timing", "lddmm_solve_opts_default",
                   "lddmm_solve", "lddmm_server_create", "lddmm_server_job_footprint",
                   "lddmm_server_submit", "lddmm_server_poll", "lddmm_server_wait",
@@ -173,8 +176,10 @@ class GradResult:
     loss: torch.Tensor       # device scalar
     H0: torch.Tensor         # device scalar
     mismatch: torch.Tensor   # device scalar, sum |q(1) - x|^2
-    grad: torch.Tensor       # [N,3]
+    grad: torch.Tensor       # [N,3] dL/dp0
     q1: torch.Tensor | None
+    grad_q0: torch.Tensor | None = None   # [N,3] dL/dq0
+    grad_x: torch.Tensor | None = None    # [N,3] dL/dtarget
 
 
 class Context:
@@ -223,8 +228,10 @@ class Context:
 
     def shoot_grad(self, q0: torch.Tensor, p0: torch.Tensor, target: torch.Tensor, T: int,
                    sigma: float, lam: float, precision="fp32c", ckpt_every: int = 0,
-                   want_q1: bool = True, stream=None, out: dict | None = None) -> GradResult:
-        """Loss of eq. 3 and its gradient w.r.t. p0 (Alg. 1 ComputeGradient).
+                   want_q1: bool = True, stream=None, out: dict | None = None,
+                   want_grad_q0: bool = False, want_grad_x: bool = False) -> GradResult:
+        """Loss of eq. 3 and its gradient w.r.t. p0 (Alg. 1 ComputeGradient);
+        optionally also w.r.t. q0 and the target (lddmm_shoot_grad_all).
 
         ``out`` may hold preallocated ``grad`` [N,3], ``out3`` [3] and ``q1``.
         """
@@ -240,6 +247,16 @@ class Context:
         q1 = out.get("q1") if want_q1 else None
         if want_q1 and q1 is None:
             q1 = torch.empty_like(q0)
+        if want_grad_q0 or want_grad_x:
+            gq = torch.empty_like(q0) if want_grad_q0 else None
+            gx = torch.empty_like(q0) if want_grad_x else None
+            _check(lib().lddmm_shoot_grad_all(
+                self._h, ctypes.byref(prm), _pts(q0, "q0", n), _pts(p0, "p0", n),
+                _pts(target, "target", n), out3.data_ptr(), _pts(grad, "grad", n),
+                gq.data_ptr() if gq is not None else None,
+                gx.data_ptr() if gx is not None else None,
+                q1.data_ptr() if q1 is not None else None, _stream(stream)), self._h)
+            return GradResult(out3[0], out3[1], out3[2], grad, q1, gq, gx)
         _check(lib().lddmm_shoot_grad(self._h, ctypes.byref(prm), _pts(q0, "q0", n),
                                       _pts(p0, "p0", n), _pts(target, "target", n),
                                       out3.data_ptr(), _pts(grad, "grad", n),

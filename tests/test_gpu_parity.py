@@ -263,3 +263,26 @@ def test_nonfinite_input_is_flagged(gpu_ctx):
     assert e.value.status == lddmm.ENONFINITE
     assert gpu_ctx.check() == lddmm.OK      # flag cleared
     torch.cuda.synchronize()
+
+
+# ----------------------------------------------------------------- gradients w.r.t. q0, target
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n,T,ckpt", [(1, 3, 0), (200, 5, 0), (2500, 6, 0), (900, 9, 4)])
+def test_gradients_wrt_q0_and_target_match_oracle(gpu_ctx, orc_mt, mode, n, T, ckpt):
+    import torch
+    pb = synth.random_problem(500 + n, n, T=T)
+    r = gpu_ctx.shoot_grad(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), T, pb.sigma, pb.lam,
+                           precision=mode, ckpt_every=ckpt, want_grad_q0=True, want_grad_x=True)
+    torch.cuda.synchronize()
+    o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, T, all_grads=True)
+    eq, ex = rel_err(host(r.grad_q0), o["grad_q0"]), rel_err(host(r.grad_x), o["grad_x"])
+    ep = rel_err(host(r.grad), o["grad"])
+    print(f"[grad_all n={n} T={T} ckpt={ckpt} {mode}] p0={ep:.2e} q0={eq:.2e} x={ex:.2e}",
+          flush=True)
+    assert max(eq, ex, ep) <= TOL[mode]
+    # the p0-gradient is the same with or without the extra outputs
+    r0 = gpu_ctx.shoot_grad(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), T, pb.sigma, pb.lam,
+                            precision=mode, ckpt_every=ckpt)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(r0.grad), host(r.grad))
