@@ -58,6 +58,11 @@ def lib():
         L.oracle_shoot_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
                                            _dp, _dp, _dp, _dp, ctypes.c_int]
         L.oracle_shoot_forward.restype = ctypes.c_int
+        L.oracle_velocity.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
+                                      _dp, ctypes.c_int]
+        L.oracle_flow.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp,
+                                  ctypes.c_int, _dp, _dp, _dp, ctypes.c_int]
+        L.oracle_flow.restype = ctypes.c_int
         L.oracle_shoot_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                         _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
         L.oracle_shoot_grad.restype = ctypes.c_int
@@ -157,6 +162,27 @@ def shoot_forward(q0, p0, sigma: float, T: int, traj: bool = False, compensated:
     if traj:
         out["traj"] = tr
     return out
+
+
+def velocity(q, p, x, sigma: float, compensated: bool = False):
+    """Velocity field of eq. 4, v(x) = sum_l g(|q_l - x|) p_l, at the points x [M,3]."""
+    q, p, x = _in(q), _in(p), _in(x)
+    v = np.empty_like(x)
+    lib().oracle_velocity(q.shape[0], x.shape[0], float(sigma), _p(q), _p(p), _p(x), _p(v),
+                          int(compensated))
+    return v
+
+
+def flow(q0, p0, x0, sigma: float, T: int, compensated: bool = False):
+    """Points x0 [M,3] carried by the landmark motion from (q0, p0) over T explicit
+    Euler steps of eq. 4's velocity.  Returns dict(x1, q1)."""
+    q0, p0, x0 = _in(q0), _in(p0), _in(x0)
+    x1, q1 = np.empty_like(x0), np.empty_like(q0)
+    rc = lib().oracle_flow(q0.shape[0], int(T), float(sigma), _p(q0), _p(p0), x0.shape[0], _p(x0),
+                           _p(x1), _p(q1), int(compensated))
+    if rc != 0:
+        raise MemoryError("oracle_flow")
+    return dict(x1=x1, q1=q1)
 
 
 def shoot_grad(q0, p0, x, sigma: float, lam: float, T: int, compensated: bool = False,

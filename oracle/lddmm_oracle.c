@@ -21,6 +21,10 @@
  *               and also dL/dq0 = a(0) + Hq(q0,p0), dL/dx = -2 lambda (q(1)-x)
  *   optimiser   L-BFGS on p0 (Sec. 2.1 and Alg. 1, steps (e)-(f)), own
  *               implementation: two-loop recursion + strong-Wolfe search
+ *   velocity    v(x,t) = sum_l g(|q_l(t) - x|) p_l(t) at any point x (eq. 4),
+ *               with the Hamiltonian's Gaussian; the flow of points moves
+ *               them by the same explicit Euler steps as the landmarks,
+ *               x(t+1) = x(t) + dt v(x(t), t) with the step-t landmark state
  *
  * Readings of passages that the extracted text garbles (eq. 1 loses the 1/2
  * and a bracket, the kernel loses its sign and the 2 sigma^2, eq. 3 says
@@ -293,6 +297,72 @@ int oracle_shoot_forward(int n, int T, double sigma, const double *q0, const dou
                          double *q1, double *p1, double *H0, double *traj, double *Hp0,
                          int compensated) {
     return shoot_forward_impl(n, T, sigma, q0, p0, q1, p1, H0, traj, Hp0, NULL, compensated);
+}
+
+/* ------------------------------------------------------------------------ */
+/* the velocity field at arbitrary points and their flow (eq. 4)            */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int n, comp; double sigma;
+    const double *q, *p, *x;
+    double *v;
+} vel_ctx;
+
+/* v(x_i) = sum_l g(|q_l - x_i|) p_l, landmarks in index order */
+static void vel_rows(void *v, int i0, int i1) {
+    vel_ctx *k = (vel_ctx *)v;
+    for (int i = i0; i < i1; ++i) {
+        const double *xi = k->x + 3 * i;
+        acc_t s[3] = {{0, 0}, {0, 0}, {0, 0}};
+        for (int l = 0; l < k->n; ++l) {
+            const double *pl = k->p + 3 * l;
+            double g = gauss(k->q + 3 * l, xi, k->sigma);
+            for (int d = 0; d < 3; ++d) acc_add(&s[d], g * pl[d], k->comp);
+        }
+        for (int d = 0; d < 3; ++d) k->v[3 * i + d] = acc_get(&s[d]);
+    }
+}
+
+/* Velocity of eq. 4 at m points x [m,3] for the landmark state (q, p) [n,3]. */
+void oracle_velocity(int n, int m, double sigma, const double *q, const double *p,
+                     const double *x, double *v, int compensated) {
+    vel_ctx k = {n, compensated, sigma, q, p, x, v};
+    for_rows(m, vel_rows, &k);
+}
+
+/* Flow of m points x0 [m,3] along the landmark motion from (q0, p0): at each
+ * of the T steps the points take the velocity of the landmark state at step
+ * t, and landmarks and points are then updated together.  x1 [m,3] receives
+ * the points at t = 1; q1 (optional) the landmarks.  Returns 0 or -2. */
+int oracle_flow(int n, int T, double sigma, const double *q0, const double *p0, int m,
+                const double *x0, double *x1, double *q1, int compensated) {
+    size_t nn = 3 * (size_t)n, mm = 3 * (size_t)m;
+    double *q = (double *)malloc(sizeof(double) * nn), *p = (double *)malloc(sizeof(double) * nn);
+    double *Hq = (double *)malloc(sizeof(double) * nn), *Hp = (double *)malloc(sizeof(double) * nn);
+    double *x = (double *)malloc(sizeof(double) * (mm ? mm : 1));
+    double *v = (double *)malloc(sizeof(double) * (mm ? mm : 1));
+    if (!q || !p || !Hq || !Hp || !x || !v) {
+        free(q); free(p); free(Hq); free(Hp); free(x); free(v);
+        return -2;
+    }
+    memcpy(q, q0, sizeof(double) * nn);
+    memcpy(p, p0, sizeof(double) * nn);
+    if (mm) memcpy(x, x0, sizeof(double) * mm);
+    const double dt = 1.0 / T;
+    for (int t = 0; t < T; ++t) {
+        oracle_pair_forward(n, sigma, q, p, Hq, Hp, compensated);
+        oracle_velocity(n, m, sigma, q, p, x, v, compensated);
+        for (size_t k = 0; k < nn; ++k) {
+            q[k] = q[k] + dt * Hp[k];
+            p[k] = p[k] - dt * Hq[k];
+        }
+        for (size_t k = 0; k < mm; ++k) x[k] = x[k] + dt * v[k];
+    }
+    if (mm) memcpy(x1, x, sizeof(double) * mm);
+    if (q1) memcpy(q1, q, sizeof(double) * nn);
+    free(q); free(p); free(Hq); free(Hp); free(x); free(v);
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -420,3 +420,112 @@ def test_gradient_wrt_q0_matches_dense_autograd_model(orc):
     r = orc.shoot_grad(q0, p0, x, sigma, lam, T, all_grads=True)
     assert rel(r["grad_q0"], gq.numpy()) < 1e-12
     assert rel(r["grad_x"], gx.numpy()) < 1e-13
+
+
+# ---------------------------------------------------------------- velocity field and flow (eq. 4)
+
+def test_velocity_at_the_landmarks_is_Hp(orc):
+    """eq. 4 evaluated at a landmark is the landmark's own velocity dq/dt = Hp (eq. 2)."""
+    q, p, _ = rand(60, 37)
+    Hq, Hp = orc.pair_forward(q, p, 1.3)
+    v = orc.velocity(q, p, q, 1.3)
+    assert rel(v, Hp) < 1e-15
+
+
+def test_velocity_hand_value_at_half_kernel(orc):
+    """One landmark at distance d = sigma sqrt(2 ln 2) from the point: the kernel is
+    exactly 1/2 (the two-point fixture's geometry), so v = p/2; at the landmark v = p."""
+    fx, arr, ev = _golden_two_point()
+    q = arr(fx["q"])[:1]
+    p = np.array([[0.3, -1.2, 2.0]])
+    x = arr(fx["q"])                       # the landmark itself and the point at distance d
+    v = orc.velocity(q, p, x, fx["sigma"])
+    np.testing.assert_allclose(v[0], p[0], rtol=0, atol=0)
+    np.testing.assert_allclose(v[1], 0.5 * p[0], rtol=1e-15)
+
+
+def test_velocity_is_linear_in_p_and_scale_covariant(orc):
+    q, p, rng = rand(61, 20)
+    p2 = rng.standard_normal((20, 3))
+    x = 2.0 * rng.standard_normal((33, 3))
+    v = orc.velocity(q, p, x, 1.1)
+    assert rel(orc.velocity(q, 2.0 * p - 3.0 * p2, x, 1.1),
+               2.0 * v - 3.0 * orc.velocity(q, p2, x, 1.1)) < 1e-13
+    # scaling every length by a (including sigma) leaves the kernel unchanged
+    assert rel(orc.velocity(4.0 * q, p, 4.0 * x, 4.4), v) < 1e-14
+
+
+def test_flow_of_the_landmarks_is_their_trajectory(orc):
+    """Points placed on the landmarks follow them: the flow uses the step-t landmark
+    state, the same dt and the same kernel as the landmarks' own Euler steps."""
+    q0, p0, rng = rand(62, 25)
+    x0 = np.concatenate([q0, 3.0 * rng.standard_normal((9, 3))])
+    f = orc.flow(q0, p0, x0, 1.2, 17)
+    s = orc.shoot_forward(q0, p0, 1.2, 17)
+    assert rel(f["x1"][:25], s["q1"]) < 1e-15
+    assert rel(f["q1"], s["q1"]) == 0.0
+
+
+def test_far_points_do_not_move(orc):
+    q0, p0, rng = rand(63, 10, spread=1.0)
+    far = np.array([[80.0, 0.0, 0.0], [0.0, -90.0, 5.0]])   # > 40 sigma: exp underflows to 0
+    f = orc.flow(q0, p0, far, 1.0, 12)
+    np.testing.assert_array_equal(f["x1"], far)
+
+
+def test_single_landmark_flow_matches_quadrature(orc):
+    """With one landmark p is constant and q(t) = q0 + t p, so a point x obeys
+    dx/dt = exp(-|q0 + t p - x|^2 / (2 sigma^2)) p: it moves along p only.
+    Writing x = x0 + u p, u solves the scalar ODE u' = exp(-(|r0|^2 + 2 (t - u) r0.p
+    + (t - u)^2 |p|^2) / (2 sigma^2)) with r0 = q0 - x0; scipy's solve_ivp
+    integrates it and the explicit Euler flow converges to it at first order."""
+    from scipy.integrate import solve_ivp
+    q0 = np.array([[0.2, -0.1, 0.4]])
+    p0 = np.array([[0.9, 0.5, -0.3]])
+    x0 = np.array([[0.7, 0.3, 0.1], [-0.5, 0.8, 0.2]])
+    sigma = 0.8
+    pp = float(p0[0] @ p0[0])
+    errs = []
+    for T in (100, 200, 400):
+        x1 = orc.flow(q0, p0, x0, sigma, T)["x1"]
+        e = 0.0
+        for k in range(2):
+            r0 = q0[0] - x0[k]
+            rr, rp = float(r0 @ r0), float(r0 @ p0[0])
+
+            def rhs(t, u, rr=rr, rp=rp):
+                w = t - u[0]
+                return [math.exp(-(rr + 2.0 * w * rp + w * w * pp) / (2.0 * sigma ** 2))]
+            sol = solve_ivp(rhs, (0.0, 1.0), [0.0], method="DOP853", rtol=1e-13, atol=1e-15)
+            exact = x0[k] + sol.y[0, -1] * p0[0]
+            e = max(e, float(np.abs(x1[k] - exact).max()))
+        errs.append(e)
+    assert errs[0] < 5e-3
+    assert 1.8 < errs[0] / errs[1] < 2.2 and 1.8 < errs[1] / errs[2] < 2.2
+
+
+def test_flow_is_equivariant_under_rigid_motion(orc):
+    q0, p0, rng = rand(64, 15)
+    x0 = 2.0 * rng.standard_normal((21, 3))
+    th = 0.7
+    Rm = np.array([[math.cos(th), -math.sin(th), 0.0], [math.sin(th), math.cos(th), 0.0],
+                   [0.0, 0.0, 1.0]])
+    sh = np.array([3.0, -1.0, 2.5])
+    f = orc.flow(q0, p0, x0, 1.4, 9)
+    g = orc.flow(q0 @ Rm.T + sh, p0 @ Rm.T, x0 @ Rm.T + sh, 1.4, 9)
+    assert rel(g["x1"], f["x1"] @ Rm.T + sh) < 1e-13
+
+
+def test_flow_does_not_fold_a_grid(orc):
+    """The flow of a smooth field is a diffeomorphism: on a grid around the
+    landmarks every cell keeps a positive Jacobian determinant."""
+    pb = synth.random_problem(65, 40, T=10)
+    lo, hi = pb.q0.min(0), pb.q0.max(0)
+    ax = [np.linspace(lo[d], hi[d], 9) for d in range(3)]
+    g = np.stack(np.meshgrid(*ax, indexing="ij"), -1).reshape(-1, 3)
+    x1 = orc.flow(pb.q0, pb.p0, g, pb.sigma, pb.T)["x1"].reshape(9, 9, 9, 3)
+    J = np.stack([np.diff(x1, axis=d)[:8, :8, :8] for d in range(3)], -1)   # [...,3 comp, 3 dir]
+    h = np.array([ax[d][1] - ax[d][0] for d in range(3)])
+    det = np.linalg.det(J / h)
+    moved = np.abs(x1.reshape(-1, 3) - g).max()
+    assert moved > 0.05 * pb.sigma and det.min() > 0.0
