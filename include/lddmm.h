@@ -233,13 +233,46 @@ lddmm_status lddmm_shoot_grad_all(lddmm_ctx* ctx, const lddmm_params* params, co
                                   double* grad_p0, double* grad_q0, double* grad_x, double* q1,
                                   void* stream);
 
+/* Velocity field of the landmark motion at arbitrary points (eq. 4, with the
+ * Hamiltonian's Gaussian): v(x_i) = sum_l exp(-|q_l - x_i|^2 / (2 sigma^2)) p_l.
+ *   params : n, sigma and precision are used (T and ckpt_every are ignored;
+ *            lambda must still be valid)
+ *   q, p   : in, [n][3] device FP64, one landmark state (q(t), p(t))
+ *   m      : number of points, >= 0 (0: nothing is launched)
+ *   x      : in, [m][3] device FP64 points
+ *   v      : out, [m][3] device FP64 velocities
+ * The pair sums run in the precision mode, as in the forward step; a
+ * point's result does not depend on m.  Errors: EINVAL, ENOMEM, EDEVICE. */
+lddmm_status lddmm_velocity(lddmm_ctx* ctx, const lddmm_params* params, const double* q,
+                            const double* p, int32_t m, const double* x, double* v,
+                            void* stream);
+
+/* The deformation applied to arbitrary points: shoots the landmarks from
+ * (q0, p0) as lddmm_shoot_forward does and carries m points along, each
+ * Euler step moving a point by dt v(x, t) (eq. 4) with the landmark state of
+ * the same step t, so that a point placed on a landmark follows it.
+ *   q0, p0 : in, [n][3] device FP64
+ *   m      : number of points, >= 0
+ *   x0     : in, [m][3] device FP64 points at t = 0
+ *   x1     : out, [m][3] device FP64 points at t = 1 (may be the same buffer
+ *            as x0)
+ *   q1, p1 : out, optional, [n][3] device FP64 landmark state at t = 1
+ * With ckpt_every = s in (0, T) only s + 1 trajectory slots are kept and the
+ * points advance segment by segment (workspace + 24 m bytes); results are
+ * bitwise the same as with the whole trajectory.  A point's result does not
+ * depend on m or on the other points.  Errors: EINVAL, ENOMEM, EDEVICE. */
+lddmm_status lddmm_flow(lddmm_ctx* ctx, const lddmm_params* params, const double* q0,
+                        const double* p0, int32_t m, const double* x0, double* x1, double* q1,
+                        double* p1, void* stream);
+
 /* Waits for the context's work on `stream` and reports whether any call
  * since the last check produced a non-finite loss (then ENONFINITE, and the
  * flag is cleared).  Errors: EINVAL, EDEVICE. */
 lddmm_status lddmm_ctx_check(lddmm_ctx* ctx, void* stream);
 
 /* Per-kernel timing, for benchmarks.  While enabled, every launch of the
- * forward and of the adjoint pair-sum kernel is bracketed by two HIP events
+ * forward and of the adjoint pair-sum kernel and of the point-flow kernel is
+ * bracketed by two HIP events
  * recorded on the call's stream (the stream the kernel runs on); durations
  * accumulate until read.  Off by default.  Errors: EINVAL. */
 typedef struct {
@@ -247,6 +280,8 @@ typedef struct {
   double adj_ms;           /* summed duration of adjoint pair-kernel launches */
   int64_t fwd_launches;
   int64_t adj_launches;
+  double flow_ms;          /* summed duration of point-flow / velocity kernel launches */
+  int64_t flow_launches;
 } lddmm_timing;
 
 lddmm_status lddmm_ctx_set_timing(lddmm_ctx* ctx, int enable);

@@ -21,11 +21,11 @@ namespace {
 
 // Event pairs bracketing pair-kernel launches (benchmark timing).
 struct Timer {
-  struct Rec { hipEvent_t ev[2]; int kind; };   // kind 0: forward, 1: adjoint
+  struct Rec { hipEvent_t ev[2]; int kind; };
   bool on = false;
   std::vector<Rec> pending, spare;
-  double ms[2] = {0.0, 0.0};
-  int64_t count[2] = {0, 0};
+  double ms[3] = {0.0, 0.0, 0.0};       // kind 0: forward, 1: adjoint, 2: point flow
+  int64_t count[3] = {0, 0, 0};
 
   // Events for the next launch of `kind`, or null when timing is off.
   hipEvent_t* take(int kind) {
@@ -280,13 +280,14 @@ hipError_t run_adjoint(const Job& j, int t0, int t1, int* cur, double* grad, hip
   return hipSuccess;
 }
 
-lddmm_status begin(lddmm_ctx* ctx, const lddmm_params* params, Job* job) {
+// extra: bytes the caller needs past the job's buffers, at ws + L.total.
+lddmm_status begin(lddmm_ctx* ctx, const lddmm_params* params, Job* job, size_t extra = 0) {
   if (!ctx) return fail(nullptr, LDDMM_EINVAL, "ctx is NULL");
   lddmm_status st = check_params(ctx, params);
   if (st != LDDMM_OK) return st;
   const Plan plan = make_plan(params->n, target_waves());
   const Layout L = make_layout(*params, plan);
-  st = ensure_ws(ctx, L.total);
+  st = ensure_ws(ctx, L.total + a256(extra));
   if (st != LDDMM_OK) return st;
   HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   *job = make_job(*params, ctx->ws);
@@ -439,6 +440,90 @@ lddmm_status lddmm_shoot_grad_all(lddmm_ctx* ctx, const lddmm_params* params, co
                   grad_q0, grad_x);
 }
 
+namespace {
+
+FlowArgs flow_args(const Job& j, int m, int W) {
+  FlowArgs a{};
+  a.n = j.p.n;
+  a.m = m;
+  a.slots = j.L.slots;
+  a.wchunk = (j.p.n + W - 1) / W;
+  a.k = j.sc.k;
+  a.dt = j.sc.dt;
+  a.traj = j.traj;
+  a.cen = j.cen;
+  return a;
+}
+
+}  // namespace
+
+lddmm_status lddmm_velocity(lddmm_ctx* ctx, const lddmm_params* params, const double* q,
+                            const double* p, int32_t m, const double* x, double* v,
+                            void* stream) {
+  if (ctx && params && (!q || !p || m < 0 || (m > 0 && (!x || !v))))
+    return fail(ctx, LDDMM_EINVAL, "q and p must not be NULL, m >= 0, x and v non-NULL if m > 0");
+  if (!params) return fail(ctx, LDDMM_EINVAL, "params is NULL");
+  lddmm_params one = *params;   // one state: no trajectory beyond slot 0
+  one.T = 1;
+  one.ckpt_every = 0;
+  Job j;
+  lddmm_status st = begin(ctx, &one, &j);
+  if (st != LDDMM_OK) return st;
+  if (m == 0) return LDDMM_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = one.n;
+  HIP_TRY(ctx, launch_centroid(q, n, j.cen, s), "centroid");
+  HIP_TRY(ctx, launch_stage(one.precision, n, q, p, nullptr, j.cen, j.sc.k, j.st, j.xc, j.slot(0), s),
+          "stage");
+  const int W = flow_waves(n);
+  FlowArgs a = flow_args(j, m, W);
+  a.t0 = 0;
+  a.t1 = 1;
+  a.x_in = x;
+  a.v_out = v;
+  HIP_TRY(ctx, launch_flow(one.precision, W, a, s, ctx->timer.take(2)), "velocity");
+  return LDDMM_OK;
+}
+
+lddmm_status lddmm_flow(lddmm_ctx* ctx, const lddmm_params* params, const double* q0,
+                        const double* p0, int32_t m, const double* x0, double* x1, double* q1,
+                        double* p1, void* stream) {
+  if (ctx && params && (!q0 || !p0 || m < 0 || (m > 0 && (!x0 || !x1))))
+    return fail(ctx, LDDMM_EINVAL,
+                "q0 and p0 must not be NULL, m >= 0, x0 and x1 non-NULL if m > 0");
+  if (!params) return fail(ctx, LDDMM_EINVAL, "params is NULL");
+  const bool seg = params->ckpt_every > 0 && params->ckpt_every < params->T;
+  Job j;
+  lddmm_status st = begin(ctx, params, &j, seg ? 3 * (size_t)(m > 0 ? m : 0) * 8 : 0);
+  if (st != LDDMM_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = params->n, T = params->T;
+  HIP_TRY(ctx, launch_centroid(q0, n, j.cen, s), "centroid");
+  HIP_TRY(ctx, launch_stage(params->precision, n, q0, p0, nullptr, j.cen, j.sc.k, j.st, j.xc,
+                            j.slot(0), s), "stage");
+  const int W = flow_waves(n);
+  double* xs = at<double>(ctx->ws, j.L.total);
+  // Segments of the landmark forward pass, each followed by the points' steps
+  // over the same records (one segment when the whole trajectory is kept).
+  const int every = seg ? params->ckpt_every : T;
+  for (int t0 = 0; t0 < T; t0 += every) {
+    const int t1 = t0 + every < T ? t0 + every : T;
+    HIP_TRY(ctx, run_forward(j, t0, t1, t0 == 0, false, s, &ctx->timer), "forward step");
+    if (m == 0) continue;
+    FlowArgs a = flow_args(j, m, W);
+    a.t0 = t0;
+    a.t1 = t1;
+    a.x_in = t0 == 0 ? x0 : nullptr;
+    a.x_out = t1 == T ? x1 : nullptr;
+    a.xs = xs;
+    HIP_TRY(ctx, launch_flow(params->precision, W, a, s, ctx->timer.take(2)), "point flow");
+  }
+  if (q1 || p1)
+    HIP_TRY(ctx, launch_forward_out(n, j.plan.nb, j.st, j.cen, j.h0p, nullptr, q1, p1, s),
+            "forward out");
+  return LDDMM_OK;
+}
+
 lddmm_status lddmm_solve_opts_default(int32_t precision, lddmm_solve_opts* o) {
   if (!o) return fail(nullptr, LDDMM_EINVAL, "opts is NULL");
   if (precision < LDDMM_FP32 || precision > LDDMM_FP64)
@@ -572,10 +657,13 @@ lddmm_status lddmm_ctx_timing(lddmm_ctx* ctx, lddmm_timing* out, int reset) {
   out->adj_ms = ctx->timer.ms[1];
   out->fwd_launches = ctx->timer.count[0];
   out->adj_launches = ctx->timer.count[1];
-  if (reset) {
-    ctx->timer.ms[0] = ctx->timer.ms[1] = 0.0;
-    ctx->timer.count[0] = ctx->timer.count[1] = 0;
-  }
+  out->flow_ms = ctx->timer.ms[2];
+  out->flow_launches = ctx->timer.count[2];
+  if (reset)
+    for (int k = 0; k < 3; ++k) {
+      ctx->timer.ms[k] = 0.0;
+      ctx->timer.count[k] = 0;
+    }
   return LDDMM_OK;
 }
 

@@ -84,6 +84,31 @@ hipError_t launch_fwd_step(int mode, const Plan& p, const FwdArgs& a, hipStream_
                            hipEvent_t* ev = nullptr);
 hipError_t launch_adj_step(int mode, const Plan& p, const AdjArgs& a, hipStream_t s,
                            hipEvent_t* ev = nullptr);
+// Points carried by the landmark motion (eq. 4): over steps [t0, t1) of a
+// stored trajectory, x <- x + dt v(x, t) with v(x, t) = sum_l g(|q_l(t) - x|)
+// p_l(t).  One lane owns one point for all the steps; the landmarks are split
+// over the W waves of a workgroup and combined in wave order every step.
+struct FlowArgs {
+  int n, m;             // landmarks, points
+  int t0, t1;           // steps
+  int slots;            // trajectory slots: step t's records are slot t % slots
+  int wchunk;           // landmarks per wave
+  double k, dt;
+  const void* traj;     // landmark records (k q, p), slot-major
+  const double* cen;    // landmark centroid; point coordinates are centred on it
+  const double* x_in;   // [m][3] uncentred points (first segment), else read xs
+  double* xs;           // [3][m] centred FP64 point state between segments
+  double* x_out;        // [m][3] uncentred points after t1 (last segment), else write xs
+  double* v_out;        // [m][3]: write v(x, t0) and take no step (t1 == t0 + 1)
+};
+
+// Waves per workgroup of the flow kernel for n landmarks (1, 2, 4, 8 or 16;
+// LDDMM_FLOW_WAVES overrides it).  It depends on n only, so a point's result
+// does not depend on how many other points are carried with it.
+int flow_waves(int n);
+hipError_t launch_flow(int mode, int W, const FlowArgs& a, hipStream_t s,
+                       hipEvent_t* ev = nullptr);
+
 // Loss and terminal adjoint: L = H0 + lambda |q(1) - x|^2, a = 2 lambda (q(1) - x), b = 0.
 // out3 = {loss, H0, mismatch}; q1/p1 (optional) receive the final state, uncentred, [n][3].
 // grad_x (optional): dL/dx = -2 lambda (q(1) - x), [n][3].

@@ -26,6 +26,7 @@
 //    the Hamiltonian and the loss are FP64 in every mode.
 #include "shoot_internal.h"
 
+#include <cstdlib>
 #include <type_traits>
 
 namespace lddmm {
@@ -379,6 +380,91 @@ template <typename R, bool COMP, int W>
 __global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
   __shared__ typename AccOf<R, COMP>::type red[W * 9 * 64];
   adj_block<R, COMP, W>(A, blockIdx.x / A.S, blockIdx.x % A.S, red);
+}
+
+// ---------------------------------------------------------------------------
+// flow of arbitrary points (eq. 4)
+// ---------------------------------------------------------------------------
+// v += sum_j g(x, q_j) p_j over landmarks j in [j0, j1) for the lane's point
+// (pre-scaled coordinates xs = k x): 9 VALU + 1 exp per pair.
+template <typename R>
+__device__ __forceinline__ void vel_range(const Rec<R>* __restrict__ Xp, R x0, R x1, R x2,
+                                          int j0, int j1, R h[3]) {
+  const GlobalPtr<Rec<R>> X = global_ptr(Xp);
+  R v0 = h[0], v1 = h[1], v2 = h[2];
+#pragma unroll 4
+  for (int j = j0; j < j1; ++j) {
+    const Rec<R> rj = load_rec<R>(X, j);
+    const R dx = x0 - rj.x, dy = x1 - rj.y, dz = x2 - rj.z;
+    R r2 = dx * dx;
+    r2 = fma(dy, dy, r2);
+    r2 = fma(dz, dz, r2);
+    const R g = ex2(-r2);
+    v0 = fma(g, rj.px, v0);
+    v1 = fma(g, rj.py, v1);
+    v2 = fma(g, rj.pz, v2);
+  }
+  h[0] = v0; h[1] = v1; h[2] = v2;
+}
+
+// One workgroup: 64 points (one per lane) through all steps [t0, t1).  Every
+// wave keeps the same FP64 copy of its lanes' points; wave w sums landmarks
+// [w wchunk, (w+1) wchunk) and the W sums are combined in wave order, so the
+// result depends on n and W only.
+template <typename R, bool COMP, int W>
+__global__ __launch_bounds__(64 * W) void k_flow(FlowArgs A) {
+  using Acc = typename AccOf<R, COMP>::type;
+  __shared__ Acc red[W > 1 ? W * 3 * 64 : 1];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int i = blockIdx.x * 64 + lane;
+  const int ic = min(i, A.m - 1);
+  double x[3];
+  for (int c = 0; c < 3; ++c)
+    x[c] = A.x_in ? A.x_in[3 * ic + c] - A.cen[c] : A.xs[(size_t)c * A.m + ic];
+  const int j0 = min(A.n, w * A.wchunk);
+  const int j1 = min(A.n, j0 + A.wchunk);
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int t = A.t0; t < A.t1; ++t) {
+    const Rec<R>* X = static_cast<const Rec<R>*>(A.traj) + (size_t)(t % A.slots) * A.n;
+    const R s0 = (R)(A.k * x[0]), s1 = (R)(A.k * x[1]), s2 = (R)(A.k * x[2]);
+    Acc o[3];
+    wave_sums<R, COMP, 3>(j0, j1, o,
+                          [&](int a, int b, auto* h) { vel_range<R>(X, s0, s1, s2, a, b, h); });
+    if constexpr (W > 1) {
+      block_combine<Acc, 3, W>(red, o, w, lane);
+      for (int c = 0; c < 3; ++c) v[c] = red[c * 64 + lane];
+      __syncthreads();   // red is rewritten by the next step
+    } else {
+      for (int c = 0; c < 3; ++c) v[c] = o[c];
+    }
+    if (A.v_out) break;
+    for (int c = 0; c < 3; ++c) x[c] = x[c] + A.dt * v[c];
+  }
+  if (w != 0 || i >= A.m) return;
+  if (A.v_out) {
+    for (int c = 0; c < 3; ++c) A.v_out[3 * i + c] = v[c];
+  } else if (A.x_out) {
+    for (int c = 0; c < 3; ++c) A.x_out[3 * i + c] = x[c] + A.cen[c];
+  } else {
+    for (int c = 0; c < 3; ++c) A.xs[(size_t)c * A.m + i] = x[c];
+  }
+}
+
+template <typename R, bool COMP>
+hipError_t flow_dispatch(int W, const FlowArgs& a, hipStream_t s, hipEvent_t* ev) {
+  const dim3 grid((unsigned)((a.m + 63) / 64));
+  if (ev) (void)hipEventRecord(ev[0], s);
+  switch (W) {
+    case 1: k_flow<R, COMP, 1><<<grid, 64, 0, s>>>(a); break;
+    case 2: k_flow<R, COMP, 2><<<grid, 128, 0, s>>>(a); break;
+    case 4: k_flow<R, COMP, 4><<<grid, 256, 0, s>>>(a); break;
+    case 8: k_flow<R, COMP, 8><<<grid, 512, 0, s>>>(a); break;
+    case 16: k_flow<R, COMP, 16><<<grid, 1024, 0, s>>>(a); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (ev) (void)hipEventRecord(ev[1], s);
+  return hipGetLastError();
 }
 
 // Split path (S > 1): combine the S workgroup partials in chunk order, then
@@ -780,6 +866,29 @@ hipError_t launch_adj_step(int mode, const Plan& p, const AdjArgs& a, hipStream_
     case kFP32: return adj_dispatch<float, false>(p, a, s, ev);
     case kFP32Comp: return adj_dispatch<float, true>(p, a, s, ev);
     case kFP64: return adj_dispatch<double, false>(p, a, s, ev);
+  }
+  return hipErrorInvalidValue;
+}
+
+int flow_waves(int n) {
+  static const int forced = [] {
+    const char* e = std::getenv("LDDMM_FLOW_WAVES");
+    return e ? std::atoi(e) : 0;
+  }();
+  if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == 16) return forced;
+  // about 4096 landmarks per wave and step keeps the per-step combine small
+  int W = 1;
+  while (W < 16 && (W * 2) * 4096 <= n) W *= 2;
+  return W;
+}
+
+hipError_t launch_flow(int mode, int W, const FlowArgs& a, hipStream_t s, hipEvent_t* ev) {
+  if (a.m <= 0 || a.n <= 0 || a.t1 <= a.t0 || a.slots <= 0) return hipErrorInvalidValue;
+  if (a.v_out && a.t1 != a.t0 + 1) return hipErrorInvalidValue;
+  switch (mode) {
+    case kFP32: return flow_dispatch<float, false>(W, a, s, ev);
+    case kFP32Comp: return flow_dispatch<float, true>(W, a, s, ev);
+    case kFP64: return flow_dispatch<double, false>(W, a, s, ev);
   }
   return hipErrorInvalidValue;
 }

@@ -33,7 +33,8 @@ class Params(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("fwd_ms", ctypes.c_double), ("adj_ms", ctypes.c_double),
-                ("fwd_launches", ctypes.c_int64), ("adj_launches", ctypes.c_int64)]
+                ("fwd_launches", ctypes.c_int64), ("adj_launches", ctypes.c_int64),
+                ("flow_ms", ctypes.c_double), ("flow_launches", ctypes.c_int64)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -91,6 +92,10 @@ def lib():
         L.lddmm_shoot_grad.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
         L.lddmm_shoot_grad_all.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp,
                                            _vp, _vp, _vp]
+        L.lddmm_velocity.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, ctypes.c_int32, _vp,
+                                     _vp, _vp]
+        L.lddmm_flow.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, ctypes.c_int32, _vp, _vp,
+                                 _vp, _vp, _vp]
         L.lddmm_ctx_check.argtypes = [_vp, _vp]
         L.lddmm_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(_vp)]
         L.lddmm_server_job_footprint.argtypes = [ctypes.POINTER(ServerConfig), ctypes.c_int32,
@@ -116,6 +121,7 @@ def lib():
         L.lddmm_version.restype = ctypes.c_char_p
         for f in ("lddmm_ctx_create", "lddmm_ctx_destroy", "lddmm_workspace_size",
                   "lddmm_shoot_forward", "lddmm_shoot_grad", "lddmm_shoot_grad_all",
+                  "lddmm_velocity", "lddmm_flow",
                   "lddmm_ctx_check",
                   "lddmm_ctx_set_timing", "lddmm_ctx_timing", "lddmm_solve_opts_default",
                   "lddmm_solve", "lddmm_server_create", "lddmm_server_job_footprint",
@@ -226,6 +232,36 @@ class Context:
                                          H0.data_ptr(), _stream(stream)), self._h)
         return q1, p1, H0
 
+    def velocity(self, q: torch.Tensor, p: torch.Tensor, x: torch.Tensor, sigma: float,
+                 precision="fp32c", stream=None, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Velocity field of eq. 4 at the points x [M,3] for the landmark state (q, p)."""
+        n, m = q.shape[0], x.shape[0]
+        prm = make_params(n, 1, sigma, 0.0, precision)
+        v = torch.empty_like(x) if out is None else out
+        _check(lib().lddmm_velocity(self._h, ctypes.byref(prm), _pts(q, "q", n), _pts(p, "p", n),
+                                    m, _pts(x, "x", m), _pts(v, "v", m), _stream(stream)),
+               self._h)
+        return v
+
+    def flow(self, q0: torch.Tensor, p0: torch.Tensor, x0: torch.Tensor, T: int, sigma: float,
+             precision="fp32c", ckpt_every: int = 0, want_landmarks: bool = False, stream=None,
+             out: torch.Tensor | None = None):
+        """Points x0 [M,3] carried along the landmark motion from (q0, p0) (eq. 4).
+
+        Returns x1, or (x1, q1, p1) with ``want_landmarks``.  ``out`` may be x0
+        itself (in place)."""
+        n, m = q0.shape[0], x0.shape[0]
+        prm = make_params(n, T, sigma, 0.0, precision, ckpt_every)
+        x1 = torch.empty_like(x0) if out is None else out
+        q1 = torch.empty_like(q0) if want_landmarks else None
+        p1 = torch.empty_like(q0) if want_landmarks else None
+        _check(lib().lddmm_flow(self._h, ctypes.byref(prm), _pts(q0, "q0", n), _pts(p0, "p0", n),
+                                m, _pts(x0, "x0", m), _pts(x1, "x1", m),
+                                q1.data_ptr() if q1 is not None else None,
+                                p1.data_ptr() if p1 is not None else None, _stream(stream)),
+               self._h)
+        return (x1, q1, p1) if want_landmarks else x1
+
     def shoot_grad(self, q0: torch.Tensor, p0: torch.Tensor, target: torch.Tensor, T: int,
                    sigma: float, lam: float, precision="fp32c", ckpt_every: int = 0,
                    want_q1: bool = True, stream=None, out: dict | None = None,
@@ -298,7 +334,8 @@ class Context:
         t = Timing()
         _check(lib().lddmm_ctx_timing(self._h, ctypes.byref(t), int(bool(reset))), self._h)
         return dict(fwd_ms=t.fwd_ms, adj_ms=t.adj_ms, fwd_launches=int(t.fwd_launches),
-                    adj_launches=int(t.adj_launches))
+                    adj_launches=int(t.adj_launches), flow_ms=t.flow_ms,
+                    flow_launches=int(t.flow_launches))
 
     def check(self, stream=None) -> int:
         """Synchronise and report a non-finite loss since the last check."""

@@ -206,3 +206,25 @@ CONFIGS = {
     3: sphere_autograd,
     5: two_blobs,
 }
+
+
+# --------------------------------------------------------------------------
+# points to deform (flow of eq. 4)
+# --------------------------------------------------------------------------
+
+def grid(lo, hi, k: int) -> np.ndarray:
+    """Regular k x k x k grid spanning the box [lo, hi], [k^3, 3] (last axis fastest)."""
+    ax = [np.linspace(float(lo[d]), float(hi[d]), k) for d in range(3)]
+    return _c(np.stack(np.meshgrid(*ax, indexing="ij"), -1).reshape(-1, 3))
+
+
+def ellipsoid_grid(k: int = 64, n: int = 4096, T: int = 40) -> tuple[Problem, np.ndarray]:
+    """The ellipsoid registration of ``ellipsoid_warp`` with the momentum
+    p0 = (x - q0) / 2, and a k^3 grid over the landmarks' bounding box grown by
+    2 sigma on every side: the voxel centres an image warp would carry."""
+    pb = ellipsoid_warp(n=n, T=T)
+    pb.p0 = _c(0.5 * (pb.target - pb.q0))
+    pad = 2.0 * pb.sigma
+    pts = grid(pb.q0.min(0) - pad, pb.q0.max(0) + pad, k)
+    pb.name = f"ellipsoid{n}_T{T}_grid{k}"
+    return pb, pts

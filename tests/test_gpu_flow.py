@@ -1,0 +1,126 @@
+"""Velocity field (eq. 4) and flow of arbitrary points on the GPU against the
+oracle: element-wise at sizes that span several tiles with ragged tails, on
+sampled points at the ellipsoid workload with a 64^3 grid, and the flow's
+own invariants (checkpointed segments and point subsets give bitwise the
+same result; points on the landmarks follow them)."""
+import numpy as np
+import pytest
+
+from paper_1907_04839_amd import synth
+
+from conftest import rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32c": 1e-5, "fp32": 1e-5}
+MODES = ["fp64", "fp32c", "fp32"]
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def pts(seed, m, spread=4.0):
+    return np.ascontiguousarray(spread * np.random.default_rng(seed).standard_normal((m, 3)))
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n,m", [(1, 1), (37, 1000), (5000, 2049), (9000, 700), (17000, 130)])
+def test_velocity_matches_oracle(gpu_ctx, orc_mt, mode, n, m):
+    import torch
+    pb = synth.random_problem(700 + n, n, T=1)
+    x = pts(800 + m, m)
+    v = gpu_ctx.velocity(to_dev(pb.q0), to_dev(pb.p0), to_dev(x), pb.sigma, precision=mode)
+    torch.cuda.synchronize()
+    ref = orc_mt.velocity(pb.q0, pb.p0, x, pb.sigma)
+    e = rel_err(host(v), ref)
+    print(f"[velocity n={n} m={m} {mode}] {e:.2e}", flush=True)
+    assert e <= TOL[mode]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n,m,T", [(1, 5, 4), (300, 1000, 7), (2500, 777, 6), (9000, 200, 3)])
+def test_flow_matches_oracle(gpu_ctx, orc_mt, mode, n, m, T):
+    import torch
+    pb = synth.random_problem(900 + n, n, T=T)
+    x0 = pts(1000 + m, m)
+    x1, q1, _ = gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), to_dev(x0), T, pb.sigma,
+                             precision=mode, want_landmarks=True)
+    torch.cuda.synchronize()
+    ref = orc_mt.flow(pb.q0, pb.p0, x0, pb.sigma, T)
+    ed = rel_err(host(x1) - x0, ref["x1"] - x0)          # error relative to the displacement
+    eq = rel_err(host(q1) - pb.q0, ref["q1"] - pb.q0)
+    print(f"[flow n={n} m={m} T={T} {mode}] points={ed:.2e} landmarks={eq:.2e}", flush=True)
+    assert ed <= TOL[mode] and eq <= TOL[mode]
+
+
+def test_empty_point_set_is_a_no_op(gpu_ctx):
+    import torch
+    pb = synth.random_problem(950, 50, T=3)
+    x = torch.empty((0, 3), dtype=torch.float64, device="cuda")
+    assert gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), x, 3, pb.sigma).shape == (0, 3)
+    assert gpu_ctx.velocity(to_dev(pb.q0), to_dev(pb.p0), x, pb.sigma).shape == (0, 3)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32c"])
+def test_checkpointed_segments_are_bitwise_identical(gpu_ctx, mode):
+    import torch
+    pb = synth.random_problem(960, 3000, T=10)
+    x0 = to_dev(pts(961, 5000))
+    full = gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), x0, 10, pb.sigma, precision=mode)
+    segs = [gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), x0, 10, pb.sigma, precision=mode,
+                         ckpt_every=s) for s in (1, 3, 4)]
+    torch.cuda.synchronize()
+    for r in segs:
+        assert torch.equal(r, full)
+
+
+def test_in_place_flow(gpu_ctx):
+    import torch
+    pb = synth.random_problem(965, 400, T=5)
+    x0 = to_dev(pts(966, 3000))
+    ref = gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), x0, 5, pb.sigma)
+    x = x0.clone()
+    gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), x, 5, pb.sigma, out=x)
+    torch.cuda.synchronize()
+    assert torch.equal(x, ref)
+
+
+@pytest.mark.parametrize("n", [700, 9000])
+def test_point_results_do_not_depend_on_the_other_points(gpu_ctx, n):
+    import torch
+    pb = synth.random_problem(970, n, T=4)
+    x0 = pts(971, 3000)
+    allr = host(gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), to_dev(x0), 4, pb.sigma))
+    idx = np.random.default_rng(972).permutation(3000)[:333]
+    sub = host(gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), to_dev(x0[idx]), 4, pb.sigma))
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(sub, allr[idx])
+
+
+def test_points_on_the_landmarks_follow_them(gpu_ctx):
+    import torch
+    pb = synth.random_problem(975, 2000, T=8)
+    x1, q1, _ = gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.q0), 8, pb.sigma,
+                             precision="fp64", want_landmarks=True)
+    torch.cuda.synchronize()
+    assert rel_err(host(x1) - pb.q0, host(q1) - pb.q0) < 1e-13
+
+
+@pytest.mark.parametrize("mode,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
+def test_ellipsoid_grid64_sampled_points_match_oracle(gpu_ctx, orc_mt, mode, tol):
+    """The full workload (4096 landmarks, T = 40, 64^3 = 262144 grid points) in
+    the launch configuration the benchmark times; the oracle flows 256 sampled
+    points (its cost is the landmark pass plus 256 x 4096 x 40 pairs)."""
+    import torch
+    pb, grid = synth.ellipsoid_grid(64)
+    x1 = host(gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), to_dev(grid), pb.T, pb.sigma,
+                           precision=mode))
+    torch.cuda.synchronize()
+    idx = np.sort(np.random.default_rng(980).choice(len(grid), 256, replace=False))
+    idx[-1] = len(grid) - 1                                   # the ragged end of the grid
+    ref = orc_mt.flow(pb.q0, pb.p0, grid[idx], pb.sigma, pb.T)["x1"]
+    e = rel_err(x1[idx] - grid[idx], ref - grid[idx])
+    moved = np.abs(x1 - grid).max()
+    print(f"[flow ellipsoid4096 grid64 {mode}] sampled={e:.2e} max move={moved:.2f}", flush=True)
+    assert e <= tol and moved > 1.0
