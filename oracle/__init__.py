@@ -68,7 +68,7 @@ def lib():
         L.oracle_shoot_grad.restype = ctypes.c_int
         L.oracle_shoot_grad_all.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                             ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-                                            _dp, _dp, ctypes.c_int]
+                                            _dp, _dp, ctypes.c_int, ctypes.c_int]
         L.oracle_shoot_grad_all.restype = ctypes.c_int
         L.oracle_solve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    _dp, _dp, _dp, ctypes.POINTER(_Opts), ctypes.POINTER(_Result),
@@ -186,11 +186,15 @@ def flow(q0, p0, x0, sigma: float, T: int, compensated: bool = False):
 
 
 def shoot_grad(q0, p0, x, sigma: float, lam: float, T: int, compensated: bool = False,
-               all_grads: bool = False):
+               all_grads: bool = False, energy: str = "initial"):
     """Loss L = H(q0,p0) + lam |q(1)-x|^2 (eq. 3) and dL/dp0 (exact discrete adjoint).
 
-    Returns dict(loss, grad, q1, H0, mismatch[, grad_q0, grad_x]).
+    energy="final" uses H(q(1),p(1)) as the energy term (the loss as Alg. 1
+    evaluates it after the forward loop).  Returns dict(loss, grad, q1, H0
+    (the energy term), mismatch[, grad_q0, grad_x]).
     """
+    if energy not in ("initial", "final"):
+        raise ValueError("energy must be 'initial' or 'final'")
     q0, p0, x = _in(q0), _in(p0), _in(x)
     n = q0.shape[0]
     grad, q1 = np.empty_like(q0), np.empty_like(q0)
@@ -200,7 +204,7 @@ def shoot_grad(q0, p0, x, sigma: float, lam: float, T: int, compensated: bool = 
     terms = np.zeros(2)
     rc = lib().oracle_shoot_grad_all(n, int(T), float(sigma), float(lam), _p(q0), _p(p0), _p(x),
                                      ctypes.byref(loss), _p(grad), _p(gq), _p(gx), _p(q1),
-                                     _p(terms), int(compensated))
+                                     _p(terms), int(compensated), int(energy == "final"))
     if rc != 0:
         raise MemoryError("oracle_shoot_grad")
     out = dict(loss=loss.value, grad=grad, q1=q1, H0=float(terms[0]), mismatch=float(terms[1]))

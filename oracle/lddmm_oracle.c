@@ -369,37 +369,52 @@ int oracle_flow(int n, int T, double sigma, const double *q0, const double *p0, 
 /* loss and gradient (Alg. 1 ComputeGradient, eq. 3)                        */
 /* ------------------------------------------------------------------------ */
 
-/* Loss and its gradients.  terms (optional): [H0, mismatch sum |q1-x|^2];
- * q1 (optional): q(1).  grad_q0, grad_x (optional): dL/dq0 = a(0) + Hq(q0,p0)
- * (the adjoint of q at t = 0 plus the energy term's own dependence on q0)
- * and dL/dx = -2 lambda (q(1) - x). */
+/* Loss and its gradients.  terms (optional): [energy term, mismatch sum
+ * |q1-x|^2]; q1 (optional): q(1).  grad_q0, grad_x (optional): dL/dq0 =
+ * a(0) + Hq(q0,p0) (the adjoint of q at t = 0 plus the energy term's own
+ * dependence on q0) and dL/dx = -2 lambda (q(1) - x).
+ *
+ * energy_final = 0: the energy term is H(q0,p0) (eq. 3).  energy_final = 1:
+ * it is H(q(1),p(1)), the energy as Alg. 1 evaluates it after the forward
+ * loop (equal to H(q0,p0) in continuous time, where H is conserved).  Then
+ * the terminal adjoint picks up dH/dq(1) = Hq(q(1),p(1)) and dH/dp(1) =
+ * Hp(q(1),p(1)), and the gradients are the adjoint at t = 0 alone. */
 int oracle_shoot_grad_all(int n, int T, double sigma, double lambda, const double *q0,
                           const double *p0, const double *x, double *loss, double *grad,
                           double *grad_q0, double *grad_x, double *q1, double *terms,
-                          int compensated) {
+                          int compensated, int energy_final) {
     size_t m = 3 * (size_t)n;
     double *traj = (double *)malloc(sizeof(double) * (size_t)(T + 1) * 2 * m);
     double *Hp0 = (double *)malloc(sizeof(double) * m), *Hq0 = (double *)malloc(sizeof(double) * m);
     double *a = (double *)malloc(sizeof(double) * m), *b = (double *)malloc(sizeof(double) * m);
     double *A = (double *)malloc(sizeof(double) * m), *B = (double *)malloc(sizeof(double) * m);
-    if (!traj || !Hp0 || !Hq0 || !a || !b || !A || !B) {
+    double *HqT = (double *)malloc(sizeof(double) * m), *HpT = (double *)malloc(sizeof(double) * m);
+    if (!traj || !Hp0 || !Hq0 || !a || !b || !A || !B || !HqT || !HpT) {
         free(traj); free(Hp0); free(Hq0); free(a); free(b); free(A); free(B);
+        free(HqT); free(HpT);
         return -2;
     }
-    double H0 = 0.0;
-    shoot_forward_impl(n, T, sigma, q0, p0, NULL, NULL, &H0, traj, Hp0, Hq0, compensated);
-    const double *qT = traj + (size_t)T * 2 * m;
+    double E = 0.0;
+    shoot_forward_impl(n, T, sigma, q0, p0, NULL, NULL, &E, traj, Hp0, Hq0, compensated);
+    const double *qT = traj + (size_t)T * 2 * m, *pT = qT + m;
+    if (energy_final) {   /* H(q(1),p(1)) = 1/2 sum_i p_i(1) . Hp_i(q(1),p(1)) */
+        oracle_pair_forward(n, sigma, qT, pT, HqT, HpT, compensated);
+        acc_t h = {0, 0};
+        for (size_t k = 0; k < m; ++k) acc_add(&h, pT[k] * HpT[k], compensated);
+        E = 0.5 * acc_get(&h);
+    }
     acc_t mis = {0, 0};
     for (size_t k = 0; k < m; ++k) {
         double r = qT[k] - x[k];
         acc_add(&mis, r * r, compensated);
         a[k] = 2.0 * lambda * r;    /* dL/dq(1) */
         b[k] = 0.0;                 /* dL/dp(1) */
+        if (energy_final) { a[k] += HqT[k]; b[k] = HpT[k]; }
         if (grad_x) grad_x[k] = -2.0 * lambda * r;
     }
     double mismatch = acc_get(&mis);
-    if (loss) *loss = H0 + lambda * mismatch;
-    if (terms) { terms[0] = H0; terms[1] = mismatch; }
+    if (loss) *loss = E + lambda * mismatch;
+    if (terms) { terms[0] = E; terms[1] = mismatch; }
     if (q1) memcpy(q1, qT, sizeof(double) * m);
     const double dt = 1.0 / T;
     for (int t = T - 1; t >= 0; --t) {
@@ -411,10 +426,10 @@ int oracle_shoot_grad_all(int n, int T, double sigma, double lambda, const doubl
         }
     }
     if (grad)
-        for (size_t k = 0; k < m; ++k) grad[k] = b[k] + Hp0[k];
+        for (size_t k = 0; k < m; ++k) grad[k] = b[k] + (energy_final ? 0.0 : Hp0[k]);
     if (grad_q0)
-        for (size_t k = 0; k < m; ++k) grad_q0[k] = a[k] + Hq0[k];
-    free(traj); free(Hp0); free(Hq0); free(a); free(b); free(A); free(B);
+        for (size_t k = 0; k < m; ++k) grad_q0[k] = a[k] + (energy_final ? 0.0 : Hq0[k]);
+    free(traj); free(Hp0); free(Hq0); free(a); free(b); free(A); free(B); free(HqT); free(HpT);
     return 0;
 }
 
@@ -422,7 +437,7 @@ int oracle_shoot_grad(int n, int T, double sigma, double lambda, const double *q
                       const double *p0, const double *x, double *loss, double *grad,
                       double *q1, double *terms, int compensated) {
     return oracle_shoot_grad_all(n, T, sigma, lambda, q0, p0, x, loss, grad, NULL, NULL, q1,
-                                 terms, compensated);
+                                 terms, compensated, 0);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -259,6 +259,20 @@ def _torch_loss(q0, p0, x, sigma, lam, T):
     return H0 + lam * ((q - x) ** 2).sum()
 
 
+def _torch_loss_final_energy(q, p, x, sigma, lam, T):
+    """The same dense model with the energy taken at t = 1."""
+    import torch
+    dt = 1.0 / T
+
+    def ham(q, p):
+        d2 = ((q[:, None, :] - q[None, :, :]) ** 2).sum(-1)
+        return 0.5 * (torch.exp(-d2 / (2 * sigma ** 2)) * (p @ p.T)).sum()
+    for _ in range(T):
+        gq, gp = torch.autograd.grad(ham(q, p), (q, p), create_graph=True)
+        q, p = q + dt * gp, p - dt * gq
+    return ham(q, p) + lam * ((q - x) ** 2).sum()
+
+
 def test_gradient_matches_dense_autograd_model(orc):
     """Independent model: dense H in torch, Hamilton's equations by autograd,
     the Euler loop unrolled, and the gradient by reverse-mode AD through it."""
@@ -529,3 +543,53 @@ def test_flow_does_not_fold_a_grid(orc):
     det = np.linalg.det(J / h)
     moved = np.abs(x1.reshape(-1, 3) - g).max()
     assert moved > 0.05 * pb.sigma and det.min() > 0.0
+
+
+# ---------------------------------------------------------------- energy taken at t = 1 (Alg. 1)
+
+def test_final_energy_variant_matches_dense_autograd_model(orc):
+    """Loss with H(q(1),p(1)) as the energy term, against an independent dense
+    torch model differentiated by reverse-mode AD (all three gradients)."""
+    import torch
+    q0, p0, rng = rand(95, 18, spread=1.5, p_scale=0.6)
+    x = q0 + rng.standard_normal(q0.shape)
+    sigma, lam, T = 1.1, 1.7, 5
+    tq, tp, tx = (torch.tensor(a, dtype=torch.float64, requires_grad=True) for a in (q0, p0, x))
+    L = _torch_loss_final_energy(tq, tp, tx, sigma, lam, T)
+    gq, gp, gx = torch.autograd.grad(L, (tq, tp, tx))
+    r = orc.shoot_grad(q0, p0, x, sigma, lam, T, all_grads=True, energy="final")
+    assert abs(r["loss"] - L.item()) < 1e-13 * abs(L.item())
+    assert rel(r["grad"], gp.numpy()) < 1e-12
+    assert rel(r["grad_q0"], gq.numpy()) < 1e-12
+    assert rel(r["grad_x"], gx.numpy()) < 1e-13
+
+
+def test_final_energy_term_is_H_of_the_final_state(orc):
+    q0, p0, rng = rand(96, 40)
+    x = q0 + rng.standard_normal(q0.shape)
+    r = orc.shoot_grad(q0, p0, x, 1.3, 0.7, 6, energy="final")
+    f = orc.shoot_forward(q0, p0, 1.3, 6)
+    assert abs(r["H0"] - orc.hamiltonian(f["q1"], f["p1"], 1.3)) < 1e-14 * abs(r["H0"])
+
+
+def test_final_energy_equals_initial_for_one_landmark(orc):
+    """One landmark: p is constant under the Euler steps, so H(q(1),p(1)) = H(q0,p0)
+    and both losses have the same gradient."""
+    q0, p0 = np.array([[0.3, -1.0, 2.0]]), np.array([[0.4, 0.1, -0.7]])
+    x = np.array([[1.0, 0.0, 1.5]])
+    a = orc.shoot_grad(q0, p0, x, 1.0, 2.0, 9, all_grads=True)
+    b = orc.shoot_grad(q0, p0, x, 1.0, 2.0, 9, all_grads=True, energy="final")
+    assert a["loss"] == b["loss"]
+    assert rel(b["grad"], a["grad"]) < 1e-15 and rel(b["grad_q0"], a["grad_q0"]) < 1e-15
+
+
+def test_final_and_initial_energy_losses_converge_as_dt_shrinks(orc):
+    """H is conserved by the continuous flow: the two losses differ by O(dt)."""
+    q0, p0, rng = rand(97, 12, spread=1.2, p_scale=0.8)
+    x = q0 + rng.standard_normal(q0.shape)
+    d = []
+    for T in (20, 40, 80):
+        a = orc.shoot_grad(q0, p0, x, 1.0, 1.0, T)
+        b = orc.shoot_grad(q0, p0, x, 1.0, 1.0, T, energy="final")
+        d.append(abs(a["loss"] - b["loss"]))
+    assert d[0] > 0 and 1.8 < d[0] / d[1] < 2.2 and 1.8 < d[1] / d[2] < 2.2
