@@ -58,6 +58,14 @@ typedef enum {
   LDDMM_FP64 = 2           /* FP64 throughout */
 } lddmm_precision;
 
+/* Energy term of the loss.  INITIAL: H(q0, p0), as in eq. 3.  FINAL:
+ * H(q(1), p(1)), the energy as Alg. 1 evaluates it after its forward loop;
+ * the two agree as dt -> 0 (H is conserved by the continuous flow).  With
+ * FINAL the gradients are the adjoint at t = 0 alone (no direct dependence
+ * of the energy on q0, p0), at the cost of one more forward pair-sum launch
+ * per evaluation.  The server supports INITIAL only. */
+typedef enum { LDDMM_ENERGY_INITIAL = 0, LDDMM_ENERGY_FINAL = 1 } lddmm_energy;
+
 typedef struct {
   int32_t n;               /* landmarks, >= 1 */
   int32_t T;               /* Euler steps, >= 1 (dt = 1/T) */
@@ -67,6 +75,7 @@ typedef struct {
   int32_t ckpt_every;      /* 0: keep the whole trajectory; s > 0: keep every
                               s-th FP64 state and recompute each segment of s
                               steps before its backward pass (same results) */
+  int32_t energy;          /* lddmm_energy: the loss's energy term */
 } lddmm_params;
 
 typedef struct lddmm_ctx lddmm_ctx;

@@ -41,6 +41,7 @@ class ShootConfig:
     precision: str = "fp32c"
     ckpt_every: int | str = "auto"     # int s >= 0, or "auto"
     traj_budget_bytes: int = 2 << 30    # trajectory memory allowed before checkpointing
+    energy: str = "initial"             # energy term H(q0,p0) ("initial") or H(q(1),p(1))
 
     def resolve_ckpt(self, n: int) -> int:
         if self.ckpt_every != "auto":
@@ -65,7 +66,8 @@ class ShootLoss(torch.autograd.Function):
         r = ctx.shoot_grad(q0.detach().contiguous(), p0.detach().contiguous(),
                            target.detach().contiguous(), cfg.T, cfg.sigma, cfg.lam,
                            precision=cfg.precision, ckpt_every=cfg.resolve_ckpt(n),
-                           want_q1=False, want_grad_q0=want_q0, want_grad_x=want_x)
+                           want_q1=False, want_grad_q0=want_q0, want_grad_x=want_x,
+                           energy=cfg.energy)
         saved = [r.grad] + ([r.grad_q0] if want_q0 else []) + ([r.grad_x] if want_x else [])
         actx.save_for_backward(*saved)
         actx.layout = (want_q0, want_x)
@@ -82,6 +84,7 @@ class ShootLoss(torch.autograd.Function):
 
 
 def shoot_loss(p0, q0, target, T: int, sigma: float, lam: float, precision: str = "fp32c",
-               ckpt_every: int | str = "auto") -> torch.Tensor:
+               ckpt_every: int | str = "auto", energy: str = "initial") -> torch.Tensor:
     """Differentiable loss of eq. 3 (with respect to p0, q0 and target)."""
-    return ShootLoss.apply(p0, q0, target, ShootConfig(T, sigma, lam, precision, ckpt_every))
+    return ShootLoss.apply(p0, q0, target,
+                           ShootConfig(T, sigma, lam, precision, ckpt_every, energy=energy))

@@ -130,6 +130,8 @@ lddmm_status check_params(lddmm_ctx* ctx, const lddmm_params* p) {
   if (p->precision < LDDMM_FP32 || p->precision > LDDMM_FP64)
     return fail(ctx, LDDMM_EINVAL, "unknown precision %d", p->precision);
   if (p->ckpt_every < 0) return fail(ctx, LDDMM_EINVAL, "ckpt_every must be >= 0");
+  if (p->energy != LDDMM_ENERGY_INITIAL && p->energy != LDDMM_ENERGY_FINAL)
+    return fail(ctx, LDDMM_EINVAL, "unknown energy term %d", p->energy);
   return LDDMM_OK;
 }
 
@@ -137,7 +139,9 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
 // Byte offsets of the workspace buffers of one problem.
 struct Layout {
-  size_t st, ad, hp0, hq0, xc, cen, h0p, out3, traj, arec, ckpt, partial, total;
+  size_t st, ad, hp0, hq0, xc, cen, h0p, out3, traj, arec, ckpt, partial;
+  size_t hpT, hqT, hTp, stT, recT;   // energy at t = 1 only (else empty)
+  size_t total;
   int slots;   // trajectory slots
   int nseg;    // checkpoint segments (0 = full trajectory)
 };
@@ -163,6 +167,12 @@ Layout make_layout(const lddmm_params& p, const Plan& plan) {
   L.arec = take(2 * n * rb);
   L.ckpt = take((size_t)L.nseg * 6 * n * 8);
   L.partial = take(plan.S > 1 ? (size_t)plan.S * 9 * n * ab : 0);
+  const bool fin = p.energy == LDDMM_ENERGY_FINAL;
+  L.hpT = take(fin ? 3 * n * 8 : 0);
+  L.hqT = take(fin ? 3 * n * 8 : 0);
+  L.hTp = take(fin ? (size_t)plan.nb * 8 : 0);
+  L.stT = take(fin ? 6 * n * 8 : 0);
+  L.recT = take(fin ? n * rb : 0);
   L.total = off;
   return L;
 }
@@ -197,6 +207,8 @@ struct Job {
   Layout L;
   void* ws;
   double *st, *ad, *hp0, *hq0, *xc, *cen, *h0p, *out3, *ckpt;
+  double *hpT, *hqT, *hTp, *stT;
+  void* recT;
   char *traj, *arec;
   void* partial;
   size_t rb;
@@ -228,6 +240,11 @@ Job make_job(const lddmm_params& p, void* ws) {
   j.traj = at<char>(ws, j.L.traj);
   j.arec = at<char>(ws, j.L.arec);
   j.partial = at<void>(ws, j.L.partial);
+  j.hpT = at<double>(ws, j.L.hpT);
+  j.hqT = at<double>(ws, j.L.hqT);
+  j.hTp = at<double>(ws, j.L.hTp);
+  j.stT = at<double>(ws, j.L.stT);
+  j.recT = at<void>(ws, j.L.recT);
   j.rb = rec_bytes(p.precision);
   return j;
 }
@@ -268,9 +285,10 @@ hipError_t run_adjoint(const Job& j, int t0, int t1, int* cur, double* grad, hip
     a.arec = j.arec_buf(*cur);
     a.arec_next = j.arec_buf(*cur ^ 1);
     a.ad = j.ad;
-    a.hp0 = j.hp0;
+    const bool fin = j.p.energy == LDDMM_ENERGY_FINAL;   // then dL/dp0 = b(0), dL/dq0 = a(0)
+    a.hp0 = fin ? nullptr : j.hp0;
     a.grad = t == 0 ? grad : nullptr;
-    a.hq0 = j.hq0;
+    a.hq0 = fin ? nullptr : j.hq0;
     a.grad_q0 = t == 0 ? grad_q0 : nullptr;
     a.partial = j.partial;
     hipError_t e = launch_adj_step(mode, j.plan, a, s, tm->take(1));
@@ -308,8 +326,28 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
             "checkpoint 0");
   HIP_TRY(ctx, run_forward(j, 0, T, true, true, s, &ctx->timer, grad_q0 != nullptr),
           "forward step");
+  const bool fin = params->energy == LDDMM_ENERGY_FINAL;
+  if (fin) {
+    // Energy at t = 1 (the loss as Alg. 1 evaluates it after the forward loop): the
+    // forward sums at the final state, taken by one more forward launch on a scratch
+    // copy of the state, so the trajectory and the state stay as they are.
+    HIP_TRY(ctx, hipMemcpyAsync(j.stT, j.st, 6 * (size_t)n * 8, hipMemcpyDeviceToDevice, s),
+            "final state copy");
+    FwdArgs a{};
+    a.n = n; a.nb = j.plan.nb; a.S = j.plan.S; a.chunk = j.plan.chunk; a.wchunk = j.plan.wchunk;
+    a.sc = j.sc;
+    a.rec_t = j.slot(T);
+    a.rec_t1 = j.recT;
+    a.st = j.stT;
+    a.hp0 = j.hpT;
+    a.hq0 = j.hqT;
+    a.h0_part = j.hTp;
+    a.partial = j.partial;
+    HIP_TRY(ctx, launch_fwd_step(mode, j.plan, a, s, ctx->timer.take(0)), "final energy");
+  }
   HIP_TRY(ctx, launch_loss(mode, n, j.plan.nb, params->lambda, j.sc.bscale, j.st, j.xc, j.cen,
-                           j.h0p, j.ad, j.arec_buf(0), out3, q1, nullptr, ctx->flag, grad_x, s),
+                           fin ? j.hTp : j.h0p, j.ad, j.arec_buf(0), out3, q1, nullptr, ctx->flag,
+                           grad_x, fin ? j.hqT : nullptr, fin ? j.hpT : nullptr, s),
           "loss");
   int cur = 0;
   if (j.L.nseg == 0) {

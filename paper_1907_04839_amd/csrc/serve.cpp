@@ -532,6 +532,8 @@ lddmm_status lddmm_server_submit(lddmm_server* s, const lddmm_params* p,
     return sfail(s, LDDMM_EINVAL, "n must be in 1..max_n");
   if (p->T != s->cfg.T || p->precision != s->cfg.precision)
     return sfail(s, LDDMM_EINVAL, "T and precision must match the server's");
+  if (p->energy != LDDMM_ENERGY_INITIAL)
+    return sfail(s, LDDMM_EINVAL, "the server takes the energy term at t = 0 only");
   if (!(p->sigma > 0.0) || !(p->lambda >= 0.0) || !std::isfinite(p->sigma) ||
       !std::isfinite(p->lambda))
     return sfail(s, LDDMM_EINVAL, "sigma must be > 0 and lambda >= 0");

@@ -62,7 +62,7 @@ struct AdjArgs {
   const void* arec;     // adjoint records (a, b_hat) entering the step
   void* arec_next;      // adjoint records leaving the step (written)
   double* ad;           // FP64 adjoint state [6][n]: a (3 rows) then b (3 rows)
-  const double* hp0;    // [3][n] Hp(q0,p0)
+  const double* hp0;    // [3][n] Hp(q0,p0), added to the gradient (null: nothing added)
   double* grad;         // [n][3] gradient, written at t == 0 (else null)
   const double* hq0;    // [3][n] Hq(q0,p0), with grad_q0
   double* grad_q0;      // [n][3] dL/dq0 = a(0) + Hq(q0,p0), at t == 0 (optional)
@@ -109,13 +109,15 @@ int flow_waves(int n);
 hipError_t launch_flow(int mode, int W, const FlowArgs& a, hipStream_t s,
                        hipEvent_t* ev = nullptr);
 
-// Loss and terminal adjoint: L = H0 + lambda |q(1) - x|^2, a = 2 lambda (q(1) - x), b = 0.
-// out3 = {loss, H0, mismatch}; q1/p1 (optional) receive the final state, uncentred, [n][3].
+// Loss and terminal adjoint: L = E + lambda |q(1) - x|^2, a = 2 lambda (q(1) - x), b = 0,
+// with the energy term E summed from h0_part.  With hqT/hpT ([3][n], the forward sums at the
+// final state) E is H(q(1), p(1)) and the terminal adjoint gains a += HqT, b = HpT.
+// out3 = {loss, E, mismatch}; q1/p1 (optional) receive the final state, uncentred, [n][3].
 // grad_x (optional): dL/dx = -2 lambda (q(1) - x), [n][3].
 hipError_t launch_loss(int mode, int n, int nb, double lambda, double bscale, const double* st,
                        const double* xc, const double* cen, const double* h0_part, double* ad,
                        void* arec0, double* out3, double* q1, double* p1, int* flag,
-                       double* grad_x, hipStream_t s);
+                       double* grad_x, const double* hqT, const double* hpT, hipStream_t s);
 // Forward-only epilogue: writes H0 (device scalar) and the final state.
 hipError_t launch_forward_out(int n, int nb, const double* st, const double* cen,
                               const double* h0_part, double* H0, double* q1, double* p1,

@@ -235,8 +235,8 @@ __device__ __forceinline__ AdjState load_adj_state(const AdjArgs& A, int i) {
   for (int c = 0; c < 3; ++c) {
     v.a[c] = A.ad[c * A.n + ic];
     v.b[c] = A.ad[(3 + c) * A.n + ic];
-    v.hp0[c] = A.grad ? A.hp0[c * A.n + ic] : 0.0;
-    v.hq0[c] = A.grad_q0 ? A.hq0[c * A.n + ic] : 0.0;
+    v.hp0[c] = (A.grad && A.hp0) ? A.hp0[c * A.n + ic] : 0.0;
+    v.hq0[c] = (A.grad_q0 && A.hq0) ? A.hq0[c * A.n + ic] : 0.0;
   }
   return v;
 }
@@ -597,22 +597,30 @@ __device__ __forceinline__ void loss_body(int n, int nb, double lambda, const do
                                           double* __restrict__ ad, Rec<R>* __restrict__ arec0,
                                           double* __restrict__ out3, double* __restrict__ q1,
                                           double* __restrict__ p1, int* __restrict__ flag,
-                                          double* __restrict__ grad_x, double* red) {
+                                          double* __restrict__ grad_x,
+                                          const double* __restrict__ hqT,
+                                          const double* __restrict__ hpT, double bscale,
+                                          double* red) {
   double mis = 0.0;
   for (int i = threadIdx.x; i < n; i += kLossThreads) {
-    double a[3];
+    double a[3], b[3];
     for (int c = 0; c < 3; ++c) {
       const double q = st[c * n + i];
       const double r = q - xc[c * n + i];
       mis += r * r;
-      a[c] = 2.0 * lambda * r;           // dL/dq(1)
+      a[c] = 2.0 * lambda * r;           // dL/dq(1) of the mismatch
+      b[c] = 0.0;                        // dL/dp(1)
+      if (grad_x) grad_x[3 * i + c] = -a[c];
+      if (hqT) {                         // energy term H(q(1), p(1))
+        a[c] += hqT[c * n + i];
+        b[c] = hpT[c * n + i];
+      }
       ad[c * n + i] = a[c];
-      ad[(3 + c) * n + i] = 0.0;         // dL/dp(1)
+      ad[(3 + c) * n + i] = b[c];
       if (q1) q1[3 * i + c] = q + cen[c];
       if (p1) p1[3 * i + c] = st[(3 + c) * n + i];
-      if (grad_x) grad_x[3 * i + c] = -a[c];
     }
-    arec0[i] = make_rec<R>(a[0], a[1], a[2], 0.0, 0.0, 0.0);   // b = 0, so b_hat = 0
+    arec0[i] = make_rec<R>(a[0], a[1], a[2], bscale * b[0], bscale * b[1], bscale * b[2]);
   }
   const double m = block_sum(mis, red);
   const double H0 = sum_h0(h0_part, nb, red);
@@ -630,9 +638,11 @@ __global__ __launch_bounds__(kLossThreads) void k_loss(
     int n, int nb, double lambda, const double* __restrict__ st, const double* __restrict__ xc,
     const double* __restrict__ cen, const double* __restrict__ h0_part, double* __restrict__ ad,
     Rec<R>* __restrict__ arec0, double* __restrict__ out3, double* __restrict__ q1,
-    double* __restrict__ p1, int* __restrict__ flag, double* __restrict__ grad_x) {
+    double* __restrict__ p1, int* __restrict__ flag, double* __restrict__ grad_x,
+    const double* __restrict__ hqT, const double* __restrict__ hpT, double bscale) {
   __shared__ double red[kLossThreads];
-  loss_body<R>(n, nb, lambda, st, xc, cen, h0_part, ad, arec0, out3, q1, p1, flag, grad_x, red);
+  loss_body<R>(n, nb, lambda, st, xc, cen, h0_part, ad, arec0, out3, q1, p1, flag, grad_x, hqT,
+               hpT, bscale, red);
 }
 
 __global__ __launch_bounds__(kLossThreads) void k_forward_out(
@@ -727,7 +737,7 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_batch(const BatchJob* __r
   const BatchJob& b = J[blockIdx.x];
   if (!job_live(b)) return;
   loss_body<R>(b.n, b.nb, b.lambda, b.st, b.xc, b.cen, b.h0p, b.ad, static_cast<Rec<R>*>(b.arec),
-               b.out3, b.q1, nullptr, b.flag, nullptr, red);
+               b.out3, b.q1, nullptr, b.flag, nullptr, nullptr, nullptr, 0.0, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -752,6 +762,7 @@ hipError_t fwd_dispatch(const Plan& p, const FwdArgs& a, hipStream_t s, hipEvent
     case 3: k_fwd_update<R, COMP, 3><<<p.nb, 64, 0, s>>>(a); break;
     case 4: k_fwd_update<R, COMP, 4><<<p.nb, 64, 0, s>>>(a); break;
     case 8: k_fwd_update<R, COMP, 8><<<p.nb, 64, 0, s>>>(a); break;
+    case 16: k_fwd_update<R, COMP, 16><<<p.nb, 64, 0, s>>>(a); break;
     default: k_fwd_update<R, COMP, 0><<<p.nb, 64, 0, s>>>(a); break;
   }
   return hipGetLastError();
@@ -776,6 +787,7 @@ hipError_t adj_dispatch(const Plan& p, const AdjArgs& a, hipStream_t s, hipEvent
     case 3: k_adj_update<R, COMP, 3><<<p.nb, 64, 0, s>>>(a); break;
     case 4: k_adj_update<R, COMP, 4><<<p.nb, 64, 0, s>>>(a); break;
     case 8: k_adj_update<R, COMP, 8><<<p.nb, 64, 0, s>>>(a); break;
+    case 16: k_adj_update<R, COMP, 16><<<p.nb, 64, 0, s>>>(a); break;
     default: k_adj_update<R, COMP, 0><<<p.nb, 64, 0, s>>>(a); break;
   }
   return hipGetLastError();
@@ -798,8 +810,13 @@ Plan make_plan(int n, int target_waves) {
   const int max_per_i = n / 32 > 1 ? n / 32 : 1;
   if (per_i > max_per_i) per_i = max_per_i;
   if (per_i < 1) per_i = 1;
+  static const int max_w = [] {
+    const char* e = std::getenv("LDDMM_MAX_WG_WAVES");
+    const int v = e ? std::atoi(e) : 0;
+    return (v == 1 || v == 2 || v == 4 || v == 8) ? v : 16;
+  }();
   int W = 1;
-  while (W * 2 <= per_i && W * 2 <= 16) W *= 2;
+  while (W * 2 <= per_i && W * 2 <= max_w) W *= 2;
   p.W = W;
   p.S = (per_i + W - 1) / W;
   if (p.S < 1) p.S = 1;
@@ -898,16 +915,15 @@ hipError_t launch_flow(int mode, int W, const FlowArgs& a, hipStream_t s, hipEve
 hipError_t launch_loss(int mode, int n, int nb, double lambda, double bscale, const double* st,
                        const double* xc, const double* cen, const double* h0_part, double* ad,
                        void* arec0, double* out3, double* q1, double* p1, int* flag,
-                       double* grad_x, hipStream_t s) {
-  (void)bscale;   // the terminal b is 0, so its scaled record is 0 too
+                       double* grad_x, const double* hqT, const double* hpT, hipStream_t s) {
   if (mode == kFP64)
     k_loss<double><<<1, kLossThreads, 0, s>>>(n, nb, lambda, st, xc, cen, h0_part, ad,
                                               static_cast<Rec<double>*>(arec0), out3, q1, p1, flag,
-                                              grad_x);
+                                              grad_x, hqT, hpT, bscale);
   else
     k_loss<float><<<1, kLossThreads, 0, s>>>(n, nb, lambda, st, xc, cen, h0_part, ad,
                                              static_cast<Rec<float>*>(arec0), out3, q1, p1, flag,
-                                             grad_x);
+                                             grad_x, hqT, hpT, bscale);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ _vp = ctypes.c_void_p
 class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("T", ctypes.c_int32), ("sigma", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("energy", ctypes.c_int32)]
 
 
 class Timing(ctypes.Structure):
@@ -140,10 +140,14 @@ def _check(rc: int, ctx=None, allow=(OK,)) -> int:
     raise LddmmError(rc, detail)
 
 
+ENERGIES = {"initial": 0, "final": 1}
+
+
 def make_params(n: int, T: int, sigma: float, lam: float, precision="fp32c",
-                ckpt_every: int = 0) -> Params:
+                ckpt_every: int = 0, energy="initial") -> Params:
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    return Params(int(n), int(T), float(sigma), float(lam), prec, int(ckpt_every))
+    en = ENERGIES[energy] if isinstance(energy, str) else int(energy)
+    return Params(int(n), int(T), float(sigma), float(lam), prec, int(ckpt_every), en)
 
 
 def solve_opts(precision="fp32c", **overrides) -> SolveOpts:
@@ -265,14 +269,15 @@ class Context:
     def shoot_grad(self, q0: torch.Tensor, p0: torch.Tensor, target: torch.Tensor, T: int,
                    sigma: float, lam: float, precision="fp32c", ckpt_every: int = 0,
                    want_q1: bool = True, stream=None, out: dict | None = None,
-                   want_grad_q0: bool = False, want_grad_x: bool = False) -> GradResult:
+                   want_grad_q0: bool = False, want_grad_x: bool = False,
+                   energy="initial") -> GradResult:
         """Loss of eq. 3 and its gradient w.r.t. p0 (Alg. 1 ComputeGradient);
         optionally also w.r.t. q0 and the target (lddmm_shoot_grad_all).
 
         ``out`` may hold preallocated ``grad`` [N,3], ``out3`` [3] and ``q1``.
         """
         n = q0.shape[0]
-        prm = make_params(n, T, sigma, lam, precision, ckpt_every)
+        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy)
         out = out or {}
         grad = out.get("grad")
         if grad is None:
@@ -302,13 +307,13 @@ class Context:
 
     def solve(self, q0: torch.Tensor, target: torch.Tensor, T: int, sigma: float, lam: float,
               precision="fp32c", p0: torch.Tensor | None = None, ckpt_every: int = 0,
-              want_trace: bool = False, stream=None, **opts) -> dict:
+              want_trace: bool = False, stream=None, energy="initial", **opts) -> dict:
         """L-BFGS registration on the GPU (Alg. 1).  ``opts`` override the
         library defaults (max_iter, m, max_fev, gtol, ftol_rel, c1, c2, init);
         passing ``p0`` selects init = 2 (start from it)."""
         import numpy as np
         n = q0.shape[0]
-        prm = make_params(n, T, sigma, lam, precision, ckpt_every)
+        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy)
         if p0 is not None:
             opts.setdefault("init", 2)
         o = solve_opts(precision, **opts)

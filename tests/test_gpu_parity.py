@@ -286,3 +286,54 @@ def test_gradients_wrt_q0_and_target_match_oracle(gpu_ctx, orc_mt, mode, n, T, c
                             precision=mode, ckpt_every=ckpt)
     torch.cuda.synchronize()
     np.testing.assert_array_equal(host(r0.grad), host(r.grad))
+
+
+# ----------------------------------------------------------------- energy term at t = 1
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n,T,ckpt", [(1, 3, 0), (300, 5, 0), (2500, 6, 0), (900, 9, 4)])
+def test_final_energy_variant_matches_oracle(gpu_ctx, orc_mt, mode, n, T, ckpt):
+    import torch
+    pb = synth.random_problem(1100 + n, n, T=T)
+    r = gpu_ctx.shoot_grad(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), T, pb.sigma, pb.lam,
+                           precision=mode, ckpt_every=ckpt, want_grad_q0=True, want_grad_x=True,
+                           energy="final")
+    torch.cuda.synchronize()
+    o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, T, all_grads=True,
+                          energy="final")
+    el = abs(r.loss.item() - o["loss"]) / abs(o["loss"])
+    eh = abs(r.H0.item() - o["H0"]) / abs(o["H0"])
+    eg = max(rel_err(host(r.grad), o["grad"]), rel_err(host(r.grad_q0), o["grad_q0"]),
+             rel_err(host(r.grad_x), o["grad_x"]))
+    print(f"[energy final n={n} T={T} ckpt={ckpt} {mode}] loss={el:.2e} H={eh:.2e} "
+          f"grads={eg:.2e}", flush=True)
+    assert max(el, eh, eg) <= TOL[mode]
+
+
+def test_final_energy_solve_is_consistent(gpu_ctx):
+    """The solver minimises the variant loss: its reported loss is the loss of the
+    returned p0, and it lies below the starting loss."""
+    import torch
+    pb = synth.random_problem(1150, 400, T=8)
+    q0, x = to_dev(pb.q0), to_dev(pb.target)
+    r = gpu_ctx.solve(q0, x, 8, pb.sigma, pb.lam, "fp64", energy="final", max_iter=30)
+    g = gpu_ctx.shoot_grad(q0, r["p0"], x, 8, pb.sigma, pb.lam, precision="fp64", energy="final")
+    L0 = gpu_ctx.shoot_grad(q0, torch.zeros_like(q0), x, 8, pb.sigma, pb.lam, precision="fp64",
+                            energy="final")
+    torch.cuda.synchronize()
+    assert abs(r["loss"] - g.loss.item()) <= 1e-12 * abs(g.loss.item())
+    assert r["loss"] < 0.5 * L0.loss.item()
+
+
+def test_server_rejects_final_energy():
+    import ctypes
+    from paper_1907_04839_amd import lddmm
+    pb = synth.random_problem(1160, 50, T=12)
+    with lddmm.Server(12, "fp32c", max_slots=2, max_n=1024, hbm_budget_bytes=64 << 20) as s:
+        prm = lddmm.make_params(pb.n, 12, pb.sigma, pb.lam, "fp32c", energy="final")
+        o = lddmm.solve_opts("fp32c")
+        jid = ctypes.c_int64(0)
+        st = lddmm.lib().lddmm_server_submit(s._h, ctypes.byref(prm), ctypes.byref(o),
+                                              pb.q0.ctypes.data, pb.target.ctypes.data, None,
+                                              ctypes.byref(jid))
+        assert st == lddmm.EINVAL
