@@ -33,10 +33,15 @@ VALU_PER_PAIR = {"fwd": 17, "adj": 38}
 # one exp2, 3 FMA = 15 flops in 10 VALU instructions.
 FLOW_FLOPS_PER_PAIR = 15
 FLOW_VALU_PER_PAIR = 10
-# Non-packed FP32 vector peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x
-# 2 flops (FMA) x 2.4 GHz.  Packed FP32 is not generated by this build.
-PEAK_FP32_NONPACKED_TFLOPS = 78.6
-PEAK_VALU_INSTR_PER_S = 256 * 4 * 16 * 2.4e9     # lane-instructions per second
+# MI355X's published vector peaks: FP32 157.3 TFLOP/s (256 CUs x 128 FMA
+# lanes per cycle x 2 flops x 2.4 GHz), FP64 78.6 TFLOP/s.  The FP32 figure is
+# the ceiling even though this build emits no packed FP32 instructions: on
+# gfx950 FP32 VALU instructions whose operands are all VGPRs issue faster than
+# one wave64 instruction per SIMD every 4 cycles (measured: v_mul_f32 at 1.57x,
+# v_fmac_f32 at 1.14x of that rate; with an SGPR operand 0.89-0.94x).
+PEAK_TFLOPS = {"fp32": 157.3, "fp32c": 157.3, "fp64": 78.6}
+# VALU lane-instructions per second at which the FP32 peak counts its FMAs.
+PEAK_VALU_INSTR_PER_S = 157.3e12 / 2
 
 
 def log(*a):
@@ -95,15 +100,15 @@ def kernel_times(ctx, dev, pb, precision, steps, ckpt_every=0):
                 fwd_launches=t["fwd_launches"], adj_launches=t["adj_launches"])
 
 
-def roofline(n, kt, traffic=None):
+def roofline(n, kt, traffic=None, precision="fp32c"):
     kind = "adj" if kt["adj_us"] >= kt["fwd_us"] else "fwd"
     dur = kt[f"{kind}_us"] * 1e-6
     pairs = float(n) * n
     achieved = FLOPS_PER_PAIR[kind] * pairs / dur / 1e12
     issue_frac = VALU_PER_PAIR[kind] * pairs / dur / PEAK_VALU_INSTR_PER_S
     return {"bound": "alu", "kernel": f"{kind}_pair", "achieved": round(achieved, 3),
-            "peak": PEAK_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4), "traffic": traffic,
+            "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_TFLOPS[precision], 4), "traffic": traffic,
             "avg_launch_us": round(kt[f"{kind}_us"], 2),
             "valu_issue_frac": round(issue_frac, 4)}
 
@@ -140,8 +145,8 @@ def flow_leg(ctx, precision: str, k: int = 64, reps: int = 3):
            "point_pairs_per_s": round(pairs / dt, 1),
            "flow_kernel_ms": round(1e3 * kern, 3),
            "roofline": {"bound": "alu", "kernel": "flow", "achieved": round(achieved, 3),
-                        "peak": PEAK_FP32_NONPACKED_TFLOPS, "unit": "TFLOP/s",
-                        "frac": round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4),
+                        "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK_TFLOPS[precision], 4),
                         "valu_issue_frac": round(FLOW_VALU_PER_PAIR * pairs / kern
                                                  / PEAK_VALU_INSTR_PER_S, 4)}}
     log(f"[bench] flow {m} points: {1e3 * dt:.2f} ms/call, kernel {1e3 * kern:.2f} ms, "
@@ -325,7 +330,7 @@ def main():
         log(f"[bench] {value:.4g} pair-interactions/s, {1e3 * dt / args.steps:.3f} ms/step, "
             f"loss {loss:.6g}")
         kt = kernel_times(ctx, dev, pb, args.precision, args.steps)
-        roof = roofline(pb.n, kt, measured_traffic(args.workload, args.precision))
+        roof = roofline(pb.n, kt, measured_traffic(args.workload, args.precision), args.precision)
         log(f"[bench] kernels: fwd {kt['fwd_us']:.2f} us, adj {kt['adj_us']:.2f} us per launch; "
             f"roofline frac {roof['frac']}")
         ctx.check()
@@ -351,7 +356,7 @@ def main():
                 sizes[name] = {"n": b.n, "T": b.T, "ckpt_every": ck,
                                "pairs_per_s": round(2 * b.T * b.n ** 2 * k / d, 1),
                                "ms_per_step": round(1e3 * d / k, 3),
-                               "roofline": roofline(b.n, bkt)}
+                               "roofline": roofline(b.n, bkt, precision=args.precision)}
                 log(f"[bench] {name}: {sizes[name]['pairs_per_s']:.4g} pair-interactions/s, "
                     f"frac {sizes[name]['roofline']['frac']}")
                 del bdev

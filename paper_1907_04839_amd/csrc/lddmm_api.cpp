@@ -84,13 +84,13 @@ namespace {
 
 thread_local std::string g_err;   // errors that have no context
 
-// Waves the pair kernels aim to keep in flight (256 CUs x 4 SIMDs x 4);
-// LDDMM_TARGET_WAVES overrides it for tuning.
+// Waves the pair kernels aim to have in a launch (256 CUs x 4 SIMDs x 16,
+// queued as resources free up); LDDMM_TARGET_WAVES overrides it for tuning.
 int target_waves() {
   static const int v = [] {
     const char* e = std::getenv("LDDMM_TARGET_WAVES");
     const int t = e ? std::atoi(e) : 0;
-    return t > 0 ? t : 4096;
+    return t > 0 ? t : 16384;
   }();
   return v;
 }
