@@ -56,6 +56,8 @@ def workload(name: str):
         pb = synth.sphere_autograd()
     elif name == "blobs65536":
         pb = synth.two_blobs()
+    elif name == "ellipsoid1847":
+        pb = synth.ellipsoid_warp(n=1847, T=40, iters=400)
     else:
         raise SystemExit(f"unknown workload {name}")
     return pb

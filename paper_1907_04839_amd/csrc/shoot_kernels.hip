@@ -804,13 +804,15 @@ Plan make_plan(int n, int target_waves) {
   Plan p{};
   p.n = n;
   p.nb = (n + 63) / 64;
-  // Waves per i-block: enough to give the chip ~target_waves waves, but at
-  // least 64 pairs per wave.  Workgroups of at most 8 waves: measured on
-  // N = 4096, 16384 and 65536, 8-wave workgroups with ~4x more waves in
-  // flight beat 16-wave ones by 3 %, 22 % and 17 % (shorter LDS combine and
-  // barriers, two workgroups per CU interleaving their phases).
+  // Waves per i-block: enough to give the chip ~target_waves waves, at most
+  // 64 and at least 16 pairs per wave.  Workgroups of at most 8 waves:
+  // measured on N = 4096, 16384 and 65536, 8-wave workgroups with up to 4x
+  // more waves beat 16-wave ones by 3 %, 22 % and 17 % (shorter LDS combine
+  // and barriers, two workgroups per CU interleaving their phases); 64 waves
+  // per i-block was the best split at N = 4096 and 16384.
   int per_i = (target_waves + p.nb - 1) / p.nb;
-  const int max_per_i = n / 64 > 1 ? n / 64 : 1;
+  if (per_i > 64) per_i = 64;
+  const int max_per_i = n / 16 > 1 ? n / 16 : 1;
   if (per_i > max_per_i) per_i = max_per_i;
   if (per_i < 1) per_i = 1;
   static const int max_w = [] {
