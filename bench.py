@@ -27,6 +27,8 @@ if ROOT not in sys.path:
 # Algorithmic work per ordered pair, in FP32 flops (an FMA counts 2, the one
 # exp2 counts 1): forward 26 + 1, adjoint 61 + 1 (see the pair kernels).
 FLOPS_PER_PAIR = {"fwd": 27, "adj": 62}
+# Planar problems (dim 2, z terms left out): forward 18, adjoint 42.
+FLOPS_PER_PAIR_PLANAR = {"fwd": 18, "adj": 42}
 # VALU instructions per pair (one exp2 is one instruction).
 VALU_PER_PAIR = {"fwd": 17, "adj": 38}
 # Point flow (eq. 4), per point-landmark pair: 3 sub, |d|^2 (1 mul + 2 FMA),
@@ -71,12 +73,12 @@ def momentum(pb):
     return pb.p0
 
 
-def time_steps(ctx, dev, pb, precision, steps, warmup, ckpt_every=0):
+def time_steps(ctx, dev, pb, precision, steps, warmup, ckpt_every=0, dim=3):
     import torch
     q0, x, p0 = dev["q0"], dev["x"], dev["p0"]
     out = dict(grad=torch.empty_like(q0), out3=torch.empty(3, dtype=torch.float64, device=q0.device))
     run = lambda: ctx.shoot_grad(q0, p0, x, pb.T, pb.sigma, pb.lam, precision=precision,  # noqa: E731
-                                 ckpt_every=ckpt_every, want_q1=False, out=out)
+                                 ckpt_every=ckpt_every, want_q1=False, out=out, dim=dim)
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
@@ -88,12 +90,12 @@ def time_steps(ctx, dev, pb, precision, steps, warmup, ckpt_every=0):
     return dt, float(out["out3"][0])
 
 
-def kernel_times(ctx, dev, pb, precision, steps, ckpt_every=0):
+def kernel_times(ctx, dev, pb, precision, steps, ckpt_every=0, dim=3):
     """Average pair-kernel durations from HIP events recorded on the launch stream."""
     ctx.timing(reset=True)
     ctx.set_timing(True)
     try:
-        time_steps(ctx, dev, pb, precision, steps, 0, ckpt_every)
+        time_steps(ctx, dev, pb, precision, steps, 0, ckpt_every, dim)
     finally:
         ctx.set_timing(False)
     t = ctx.timing(reset=True)
@@ -102,11 +104,11 @@ def kernel_times(ctx, dev, pb, precision, steps, ckpt_every=0):
                 fwd_launches=t["fwd_launches"], adj_launches=t["adj_launches"])
 
 
-def roofline(n, kt, traffic=None, precision="fp32c"):
+def roofline(n, kt, traffic=None, precision="fp32c", flops=FLOPS_PER_PAIR):
     kind = "adj" if kt["adj_us"] >= kt["fwd_us"] else "fwd"
     dur = kt[f"{kind}_us"] * 1e-6
     pairs = float(n) * n
-    achieved = FLOPS_PER_PAIR[kind] * pairs / dur / 1e12
+    achieved = flops[kind] * pairs / dur / 1e12
     issue_frac = VALU_PER_PAIR[kind] * pairs / dur / PEAK_VALU_INSTR_PER_S
     return {"bound": "alu", "kernel": f"{kind}_pair", "achieved": round(achieved, 3),
             "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
@@ -249,6 +251,28 @@ def full_solve(ctx, dev, pb, precision):
     return out
 
 
+def planar_leg(ctx, precision, steps=10):
+    """The planar ellipse workload (4096 landmarks in the plane z = 0, T = 40)
+    through the 2D-specialised pair loops and, for comparison, the 3D ones."""
+    import torch
+    from paper_1907_04839_amd import synth
+    pb = synth.ellipse_warp()
+    dev = {k: torch.from_numpy(v).cuda() for k, v in
+           (("q0", pb.q0), ("x", pb.target), ("p0", momentum(pb)))}
+    pairs = 2 * pb.T * pb.n ** 2
+    d2, _ = time_steps(ctx, dev, pb, precision, steps, 2, dim=2)
+    d3, _ = time_steps(ctx, dev, pb, precision, steps, 2, dim=3)
+    kt = kernel_times(ctx, dev, pb, precision, 2, dim=2)
+    out = {"workload": f"{pb.name}: N={pb.n} planar landmarks, T={pb.T}",
+           "pairs_per_s": round(pairs * steps / d2, 1),
+           "pairs_per_s_3d_loops": round(pairs * steps / d3, 1),
+           "speedup": round(d3 / d2, 3),
+           "roofline": roofline(pb.n, kt, precision=precision, flops=FLOPS_PER_PAIR_PLANAR)}
+    log(f"[bench] planar: {out['pairs_per_s']:.4g} pair-interactions/s "
+        f"({out['speedup']:.2f}x the 3D loops)")
+    return out
+
+
 def paper_scale_solve(ctx, precision):
     """A registration at the scale of the paper's own experiment (1847 landmarks,
     T = 40, up to 400 L-BFGS iterations), on the synthetic ellipsoid recipe: the
@@ -365,6 +389,7 @@ def main():
             extra["sizes"] = sizes
             extra["flow"] = flow_leg(ctx, args.precision)
             extra["paper_scale_solve"] = paper_scale_solve(ctx, args.precision)
+            extra["planar"] = planar_leg(ctx, args.precision)
 
     if args.serve_jobs > 0 and not args.quick:
         extra["serving"] = serving(args.serve_jobs)

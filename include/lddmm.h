@@ -76,6 +76,12 @@ typedef struct {
                               s-th FP64 state and recompute each segment of s
                               steps before its backward pass (same results) */
   int32_t energy;          /* lddmm_energy: the loss's energy term */
+  int32_t dim;             /* 3 (or 0): landmarks in 3D.  2: planar problem, the
+                              z components of every input are 0; the pair sums
+                              leave the z terms out (about 30 % fewer
+                              instructions per pair) and every z output is 0.
+                              Inputs with a non-zero z give undefined results.
+                              The server solves 3D problems only. */
 } lddmm_params;
 
 typedef struct lddmm_ctx lddmm_ctx;

@@ -42,6 +42,7 @@ class ShootConfig:
     ckpt_every: int | str = "auto"     # int s >= 0, or "auto"
     traj_budget_bytes: int = 2 << 30    # trajectory memory allowed before checkpointing
     energy: str = "initial"             # energy term H(q0,p0) ("initial") or H(q(1),p(1))
+    dim: int = 3                        # 2: planar problem (every z component 0)
 
     def resolve_ckpt(self, n: int) -> int:
         if self.ckpt_every != "auto":
@@ -67,7 +68,7 @@ class ShootLoss(torch.autograd.Function):
                            target.detach().contiguous(), cfg.T, cfg.sigma, cfg.lam,
                            precision=cfg.precision, ckpt_every=cfg.resolve_ckpt(n),
                            want_q1=False, want_grad_q0=want_q0, want_grad_x=want_x,
-                           energy=cfg.energy)
+                           energy=cfg.energy, dim=cfg.dim)
         saved = [r.grad] + ([r.grad_q0] if want_q0 else []) + ([r.grad_x] if want_x else [])
         actx.save_for_backward(*saved)
         actx.layout = (want_q0, want_x)

@@ -132,6 +132,8 @@ lddmm_status check_params(lddmm_ctx* ctx, const lddmm_params* p) {
   if (p->ckpt_every < 0) return fail(ctx, LDDMM_EINVAL, "ckpt_every must be >= 0");
   if (p->energy != LDDMM_ENERGY_INITIAL && p->energy != LDDMM_ENERGY_FINAL)
     return fail(ctx, LDDMM_EINVAL, "unknown energy term %d", p->energy);
+  if (p->dim != 0 && p->dim != 2 && p->dim != 3)
+    return fail(ctx, LDDMM_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
   return LDDMM_OK;
 }
 
@@ -212,6 +214,7 @@ struct Job {
   char *traj, *arec;
   void* partial;
   size_t rb;
+  int dim;   // 2 (planar) or 3
 
   void* slot(int t) const {
     const int k = L.nseg > 0 ? t % L.slots : t;
@@ -246,6 +249,7 @@ Job make_job(const lddmm_params& p, void* ws) {
   j.stT = at<double>(ws, j.L.stT);
   j.recT = at<void>(ws, j.L.recT);
   j.rb = rec_bytes(p.precision);
+  j.dim = p.dim == 2 ? 2 : 3;
   return j;
 }
 
@@ -256,6 +260,7 @@ hipError_t run_forward(const Job& j, int t0, int t1, bool first, bool store_ckpt
   for (int t = t0; t < t1; ++t) {
     FwdArgs a{};
     a.n = j.p.n; a.nb = j.plan.nb; a.S = j.plan.S; a.chunk = j.plan.chunk; a.wchunk = j.plan.wchunk;
+    a.dim = j.dim;
     a.sc = j.sc;
     a.rec_t = j.slot(t);
     a.rec_t1 = j.slot(t + 1);
@@ -280,6 +285,7 @@ hipError_t run_adjoint(const Job& j, int t0, int t1, int* cur, double* grad, hip
   for (int t = t1 - 1; t >= t0; --t) {
     AdjArgs a{};
     a.n = j.p.n; a.nb = j.plan.nb; a.S = j.plan.S; a.chunk = j.plan.chunk; a.wchunk = j.plan.wchunk;
+    a.dim = j.dim;
     a.sc = j.sc;
     a.rec_t = j.slot(t);
     a.arec = j.arec_buf(*cur);
@@ -335,6 +341,7 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
             "final state copy");
     FwdArgs a{};
     a.n = n; a.nb = j.plan.nb; a.S = j.plan.S; a.chunk = j.plan.chunk; a.wchunk = j.plan.wchunk;
+    a.dim = j.dim;
     a.sc = j.sc;
     a.rec_t = j.slot(T);
     a.rec_t1 = j.recT;
@@ -486,6 +493,7 @@ FlowArgs flow_args(const Job& j, int m, int W) {
   a.m = m;
   a.slots = j.L.slots;
   a.wchunk = (j.p.n + W - 1) / W;
+  a.dim = j.dim;
   a.k = j.sc.k;
   a.dt = j.sc.dt;
   a.traj = j.traj;

@@ -43,6 +43,7 @@ Scales make_scales(double sigma, int T);
 // Arguments of one forward Euler step (pair sums + update).
 struct FwdArgs {
   int n, nb, S, chunk, wchunk;
+  int dim;              // 3, or 2 for planar problems (z terms left out)
   Scales sc;
   const void* rec_t;    // point records at step t (k q, p)
   void* rec_t1;         // point records at step t+1 (written)
@@ -57,6 +58,7 @@ struct FwdArgs {
 // Arguments of one backward (adjoint) Euler step.
 struct AdjArgs {
   int n, nb, S, chunk, wchunk;
+  int dim;              // 3, or 2 for planar problems
   Scales sc;
   const void* rec_t;    // point records at step t (k q, p)
   const void* arec;     // adjoint records (a, b_hat) entering the step
@@ -93,6 +95,7 @@ struct FlowArgs {
   int t0, t1;           // steps
   int slots;            // trajectory slots: step t's records are slot t % slots
   int wchunk;           // landmarks per wave
+  int dim;              // 3, or 2 for planar problems
   double k, dt;
   const void* traj;     // landmark records (k q, p), slot-major
   const double* cen;    // landmark centroid; point coordinates are centred on it

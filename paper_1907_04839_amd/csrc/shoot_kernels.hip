@@ -94,8 +94,11 @@ __device__ __forceinline__ Rec<R> make_rec(double x, double y, double z, double 
 // forward pair sums over j in [j0, j1) for the lane's landmark i:
 //   h[0..2] += sum_j g_ij p_j                      (Hp)
 //   h[3..5] += sum_j g_ij (p_i . p_j) (kq_i - kq_j)  (Hq up to the factor -c/k)
+// D = 2 is the planar specialisation: the z terms are left out (every z is 0
+// there), which leaves 11 VALU + 1 exp per pair.  On planar data the two
+// forms give bitwise the same sums: each z term the 3D loop adds is an exact 0.
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int D>
 __device__ __forceinline__ void fwd_range(const Rec<R>* __restrict__ Xp, const Rec<R>& ri, int j0,
                                           int j1, R h[6]) {
   const GlobalPtr<Rec<R>> X = global_ptr(Xp);
@@ -103,21 +106,25 @@ __device__ __forceinline__ void fwd_range(const Rec<R>* __restrict__ Xp, const R
 #pragma unroll 4
   for (int j = j0; j < j1; ++j) {
     const Rec<R> rj = load_rec<R>(X, j);
-    const R dx = ri.x - rj.x, dy = ri.y - rj.y, dz = ri.z - rj.z;
+    const R dx = ri.x - rj.x, dy = ri.y - rj.y;
     R r2 = dx * dx;
     r2 = fma(dy, dy, r2);
-    r2 = fma(dz, dz, r2);
+    R dz = (R)0;
+    if constexpr (D == 3) {
+      dz = ri.z - rj.z;
+      r2 = fma(dz, dz, r2);
+    }
     const R g = ex2(-r2);
     hp0 = fma(g, rj.px, hp0);
     hp1 = fma(g, rj.py, hp1);
-    hp2 = fma(g, rj.pz, hp2);
+    if constexpr (D == 3) hp2 = fma(g, rj.pz, hp2);
     R s = ri.px * rj.px;
     s = fma(ri.py, rj.py, s);
-    s = fma(ri.pz, rj.pz, s);
+    if constexpr (D == 3) s = fma(ri.pz, rj.pz, s);
     const R gs = g * s;
     hq0 = fma(gs, dx, hq0);
     hq1 = fma(gs, dy, hq1);
-    hq2 = fma(gs, dz, hq2);
+    if constexpr (D == 3) hq2 = fma(gs, dz, hq2);
   }
   h[0] = hp0; h[1] = hp1; h[2] = hp2; h[3] = hq0; h[4] = hq1; h[5] = hq2;
 }
@@ -130,7 +137,7 @@ __device__ __forceinline__ void fwd_range(const Rec<R>* __restrict__ Xp, const R
 //   h[6..8] += sum_j g (a_j + e p_j)       (B)
 // and A = (c/k)(A1/kappa - A2).
 // ---------------------------------------------------------------------------
-template <typename R>
+template <typename R, int D>
 __device__ __forceinline__ void adj_range(const Rec<R>* __restrict__ Xp,
                                           const Rec<R>* __restrict__ Yp, const Rec<R>& ri,
                                           const Rec<R>& yi, int j0, int j1, R h[9]) {
@@ -138,43 +145,46 @@ __device__ __forceinline__ void adj_range(const Rec<R>* __restrict__ Xp,
   const GlobalPtr<Rec<R>> Y = global_ptr(Yp);
   R a10 = h[0], a11 = h[1], a12 = h[2], a20 = h[3], a21 = h[4], a22 = h[5];
   R b0 = h[6], b1 = h[7], b2 = h[8];
+  constexpr bool Z = D == 3;   // planar (D = 2): the z terms are all 0 and left out
 #pragma unroll 2
   for (int j = j0; j < j1; ++j) {
     const Rec<R> rj = load_rec<R>(X, j);
     const Rec<R> yj = load_rec<R>(Y, j);
-    const R dx = ri.x - rj.x, dy = ri.y - rj.y, dz = ri.z - rj.z;
+    const R dx = ri.x - rj.x, dy = ri.y - rj.y;
+    const R dz = Z ? ri.z - rj.z : (R)0;
     R r2 = dx * dx;
     r2 = fma(dy, dy, r2);
-    r2 = fma(dz, dz, r2);
+    if constexpr (Z) r2 = fma(dz, dz, r2);
     const R g = ex2(-r2);
-    const R ex = yi.px - yj.px, ey = yi.py - yj.py, ez = yi.pz - yj.pz;
+    const R ex = yi.px - yj.px, ey = yi.py - yj.py;
+    const R ez = Z ? yi.pz - yj.pz : (R)0;
     R e = dx * ex;
     e = fma(dy, ey, e);
-    e = fma(dz, ez, e);
+    if constexpr (Z) e = fma(dz, ez, e);
     R s = ri.px * rj.px;
     s = fma(ri.py, rj.py, s);
-    s = fma(ri.pz, rj.pz, s);
+    if constexpr (Z) s = fma(ri.pz, rj.pz, s);
     R pi = yi.x * rj.px;
     pi = fma(yi.y, rj.py, pi);
-    pi = fma(yi.z, rj.pz, pi);
+    if constexpr (Z) pi = fma(yi.z, rj.pz, pi);
     pi = fma(ri.px, yj.x, pi);
     pi = fma(ri.py, yj.y, pi);
-    pi = fma(ri.pz, yj.z, pi);
+    if constexpr (Z) pi = fma(ri.pz, yj.z, pi);
     const R gs = g * s;
     const R v = g * fma(s, e, pi);
     a10 = fma(gs, ex, a10);
     a11 = fma(gs, ey, a11);
-    a12 = fma(gs, ez, a12);
+    if constexpr (Z) a12 = fma(gs, ez, a12);
     a20 = fma(v, dx, a20);
     a21 = fma(v, dy, a21);
-    a22 = fma(v, dz, a22);
+    if constexpr (Z) a22 = fma(v, dz, a22);
     const R ge = g * e;
     b0 = fma(g, yj.x, b0);
     b1 = fma(g, yj.y, b1);
-    b2 = fma(g, yj.z, b2);
+    if constexpr (Z) b2 = fma(g, yj.z, b2);
     b0 = fma(ge, rj.px, b0);
     b1 = fma(ge, rj.py, b1);
-    b2 = fma(ge, rj.pz, b2);
+    if constexpr (Z) b2 = fma(ge, rj.pz, b2);
   }
   h[0] = a10; h[1] = a11; h[2] = a12; h[3] = a20; h[4] = a21; h[5] = a22;
   h[6] = b0; h[7] = b1; h[8] = b2;
@@ -300,7 +310,7 @@ __device__ __forceinline__ void adj_finish(const AdjArgs& A, int ib, int lane, A
 // per lane) against j-chunk s, split over the W waves.  With S == 1 the sums
 // are final and wave 0 applies the Euler update; otherwise the workgroup
 // writes its partial for the combine kernel.  red: W*C*64 accumulators of LDS.
-template <typename R, bool COMP, int W>
+template <typename R, bool COMP, int W, int D>
 __device__ __forceinline__ void fwd_block(const FwdArgs& A, int ib, int s,
                                           typename AccOf<R, COMP>::type* red) {
   using Acc = typename AccOf<R, COMP>::type;
@@ -316,7 +326,8 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& A, int ib, int s,
   FwdState v{};
   if (A.S == 1 && w == 0) v = load_fwd_state(A, ib * 64 + lane);
   Acc o[NC];
-  wave_sums<R, COMP, NC>(j0, j1, o, [&](int a, int b, auto* h) { fwd_range<R>(X, ri, a, b, h); });
+  wave_sums<R, COMP, NC>(j0, j1, o,
+                         [&](int a, int b, auto* h) { fwd_range<R, D>(X, ri, a, b, h); });
   block_combine<Acc, NC, W>(red, o, w, lane);
   if (A.S == 1) {
     if (w == 0) {
@@ -333,7 +344,7 @@ __device__ __forceinline__ void fwd_block(const FwdArgs& A, int ib, int s,
   }
 }
 
-template <typename R, bool COMP, int W>
+template <typename R, bool COMP, int W, int D>
 __device__ __forceinline__ void adj_block(const AdjArgs& A, int ib, int s,
                                           typename AccOf<R, COMP>::type* red) {
   using Acc = typename AccOf<R, COMP>::type;
@@ -353,7 +364,7 @@ __device__ __forceinline__ void adj_block(const AdjArgs& A, int ib, int s,
   if (A.S == 1 && w == 0) v = load_adj_state(A, ib * 64 + lane);
   Acc o[NC];
   wave_sums<R, COMP, NC>(j0, j1, o,
-                         [&](int a, int b, auto* h) { adj_range<R>(X, Y, ri, yi, a, b, h); });
+                         [&](int a, int b, auto* h) { adj_range<R, D>(X, Y, ri, yi, a, b, h); });
   block_combine<Acc, NC, W>(red, o, w, lane);
   if (A.S == 1) {
     if (w == 0) {
@@ -370,16 +381,16 @@ __device__ __forceinline__ void adj_block(const AdjArgs& A, int ib, int s,
   }
 }
 
-template <typename R, bool COMP, int W>
+template <typename R, bool COMP, int W, int D>
 __global__ __launch_bounds__(64 * W) void k_fwd(FwdArgs A) {
   __shared__ typename AccOf<R, COMP>::type red[W * 6 * 64];
-  fwd_block<R, COMP, W>(A, blockIdx.x / A.S, blockIdx.x % A.S, red);
+  fwd_block<R, COMP, W, D>(A, blockIdx.x / A.S, blockIdx.x % A.S, red);
 }
 
-template <typename R, bool COMP, int W>
+template <typename R, bool COMP, int W, int D>
 __global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
   __shared__ typename AccOf<R, COMP>::type red[W * 9 * 64];
-  adj_block<R, COMP, W>(A, blockIdx.x / A.S, blockIdx.x % A.S, red);
+  adj_block<R, COMP, W, D>(A, blockIdx.x / A.S, blockIdx.x % A.S, red);
 }
 
 // ---------------------------------------------------------------------------
@@ -387,7 +398,7 @@ __global__ __launch_bounds__(64 * W) void k_adj(AdjArgs A) {
 // ---------------------------------------------------------------------------
 // v += sum_j g(x, q_j) p_j over landmarks j in [j0, j1) for the lane's point
 // (pre-scaled coordinates xs = k x): 9 VALU + 1 exp per pair.
-template <typename R>
+template <typename R, int D>
 __device__ __forceinline__ void vel_range(const Rec<R>* __restrict__ Xp, R x0, R x1, R x2,
                                           int j0, int j1, R h[3]) {
   const GlobalPtr<Rec<R>> X = global_ptr(Xp);
@@ -395,14 +406,17 @@ __device__ __forceinline__ void vel_range(const Rec<R>* __restrict__ Xp, R x0, R
 #pragma unroll 4
   for (int j = j0; j < j1; ++j) {
     const Rec<R> rj = load_rec<R>(X, j);
-    const R dx = x0 - rj.x, dy = x1 - rj.y, dz = x2 - rj.z;
+    const R dx = x0 - rj.x, dy = x1 - rj.y;
     R r2 = dx * dx;
     r2 = fma(dy, dy, r2);
-    r2 = fma(dz, dz, r2);
+    if constexpr (D == 3) {
+      const R dz = x2 - rj.z;
+      r2 = fma(dz, dz, r2);
+    }
     const R g = ex2(-r2);
     v0 = fma(g, rj.px, v0);
     v1 = fma(g, rj.py, v1);
-    v2 = fma(g, rj.pz, v2);
+    if constexpr (D == 3) v2 = fma(g, rj.pz, v2);
   }
   h[0] = v0; h[1] = v1; h[2] = v2;
 }
@@ -411,7 +425,7 @@ __device__ __forceinline__ void vel_range(const Rec<R>* __restrict__ Xp, R x0, R
 // wave keeps the same FP64 copy of its lanes' points; wave w sums landmarks
 // [w wchunk, (w+1) wchunk) and the W sums are combined in wave order, so the
 // result depends on n and W only.
-template <typename R, bool COMP, int W>
+template <typename R, bool COMP, int W, int D>
 __global__ __launch_bounds__(64 * W) void k_flow(FlowArgs A) {
   using Acc = typename AccOf<R, COMP>::type;
   __shared__ Acc red[W > 1 ? W * 3 * 64 : 1];
@@ -430,7 +444,7 @@ __global__ __launch_bounds__(64 * W) void k_flow(FlowArgs A) {
     const R s0 = (R)(A.k * x[0]), s1 = (R)(A.k * x[1]), s2 = (R)(A.k * x[2]);
     Acc o[3];
     wave_sums<R, COMP, 3>(j0, j1, o,
-                          [&](int a, int b, auto* h) { vel_range<R>(X, s0, s1, s2, a, b, h); });
+                          [&](int a, int b, auto* h) { vel_range<R, D>(X, s0, s1, s2, a, b, h); });
     if constexpr (W > 1) {
       block_combine<Acc, 3, W>(red, o, w, lane);
       for (int c = 0; c < 3; ++c) v[c] = red[c * 64 + lane];
@@ -451,18 +465,28 @@ __global__ __launch_bounds__(64 * W) void k_flow(FlowArgs A) {
   }
 }
 
+// Launch KERNEL<targs..., W, D> with W waves per workgroup (1, 2, 4, 8 or 16)
+// for planar (D = 2) or 3D (D = 3) problems; other W: invalid value.
+#define LDDMM_LAUNCH_WD(W, D, grid, s, args, KERNEL, ...)                     \
+  switch ((D) == 2 ? (W) : -(W)) {                                            \
+    case 1: KERNEL<__VA_ARGS__, 1, 2><<<grid, 64, 0, s>>>(args); break;       \
+    case 2: KERNEL<__VA_ARGS__, 2, 2><<<grid, 128, 0, s>>>(args); break;      \
+    case 4: KERNEL<__VA_ARGS__, 4, 2><<<grid, 256, 0, s>>>(args); break;      \
+    case 8: KERNEL<__VA_ARGS__, 8, 2><<<grid, 512, 0, s>>>(args); break;      \
+    case 16: KERNEL<__VA_ARGS__, 16, 2><<<grid, 1024, 0, s>>>(args); break;   \
+    case -1: KERNEL<__VA_ARGS__, 1, 3><<<grid, 64, 0, s>>>(args); break;      \
+    case -2: KERNEL<__VA_ARGS__, 2, 3><<<grid, 128, 0, s>>>(args); break;     \
+    case -4: KERNEL<__VA_ARGS__, 4, 3><<<grid, 256, 0, s>>>(args); break;     \
+    case -8: KERNEL<__VA_ARGS__, 8, 3><<<grid, 512, 0, s>>>(args); break;     \
+    case -16: KERNEL<__VA_ARGS__, 16, 3><<<grid, 1024, 0, s>>>(args); break;  \
+    default: return hipErrorInvalidValue;                                     \
+  }
+
 template <typename R, bool COMP>
 hipError_t flow_dispatch(int W, const FlowArgs& a, hipStream_t s, hipEvent_t* ev) {
   const dim3 grid((unsigned)((a.m + 63) / 64));
   if (ev) (void)hipEventRecord(ev[0], s);
-  switch (W) {
-    case 1: k_flow<R, COMP, 1><<<grid, 64, 0, s>>>(a); break;
-    case 2: k_flow<R, COMP, 2><<<grid, 128, 0, s>>>(a); break;
-    case 4: k_flow<R, COMP, 4><<<grid, 256, 0, s>>>(a); break;
-    case 8: k_flow<R, COMP, 8><<<grid, 512, 0, s>>>(a); break;
-    case 16: k_flow<R, COMP, 16><<<grid, 1024, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;
-  }
+  LDDMM_LAUNCH_WD(W, a.dim, grid, s, a, k_flow, R, COMP)
   if (ev) (void)hipEventRecord(ev[1], s);
   return hipGetLastError();
 }
@@ -686,6 +710,7 @@ template <typename R>
 __device__ __forceinline__ FwdArgs batch_fwd_args(const BatchJob& b, int t) {
   FwdArgs A{};
   A.n = b.n; A.nb = b.nb; A.S = 1; A.chunk = b.n; A.wchunk = (b.n + kBatchWaves - 1) / kBatchWaves;
+  A.dim = 3;
   A.sc = b.sc;
   A.rec_t = static_cast<const Rec<R>*>(b.traj) + (size_t)t * b.n;
   A.rec_t1 = static_cast<Rec<R>*>(b.traj) + (size_t)(t + 1) * b.n;
@@ -705,7 +730,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_fwd_batch(const BatchJob* 
   const int2 it = items[blockIdx.x];
   const BatchJob& b = J[it.x];
   if (!job_live(b)) return;
-  fwd_block<R, COMP, kBatchWaves>(batch_fwd_args<R>(b, t), it.y, 0, red);
+  fwd_block<R, COMP, kBatchWaves, 3>(batch_fwd_args<R>(b, t), it.y, 0, red);
 }
 
 template <typename R, bool COMP>
@@ -720,6 +745,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_adj_batch(const BatchJob* 
   if (!job_live(b)) return;
   AdjArgs A{};
   A.n = b.n; A.nb = b.nb; A.S = 1; A.chunk = b.n; A.wchunk = (b.n + kBatchWaves - 1) / kBatchWaves;
+  A.dim = 3;
   A.sc = b.sc;
   const int cur = (T - 1 - t) & 1;   // the loss kernel fills adjoint buffer 0 for t = T-1
   A.rec_t = static_cast<const Rec<R>*>(b.traj) + (size_t)t * b.n;
@@ -728,7 +754,7 @@ __global__ __launch_bounds__(64 * kBatchWaves) void k_adj_batch(const BatchJob* 
   A.ad = b.ad;
   A.hp0 = b.hp0;
   A.grad = t == 0 ? b.grad : nullptr;
-  adj_block<R, COMP, kBatchWaves>(A, it.y, 0, red);
+  adj_block<R, COMP, kBatchWaves, 3>(A, it.y, 0, red);
 }
 
 template <typename R>
@@ -747,14 +773,7 @@ template <typename R, bool COMP>
 hipError_t fwd_dispatch(const Plan& p, const FwdArgs& a, hipStream_t s, hipEvent_t* ev) {
   const dim3 grid(p.nb * p.S);
   if (ev) (void)hipEventRecord(ev[0], s);
-  switch (p.W) {
-    case 1: k_fwd<R, COMP, 1><<<grid, 64, 0, s>>>(a); break;
-    case 2: k_fwd<R, COMP, 2><<<grid, 128, 0, s>>>(a); break;
-    case 4: k_fwd<R, COMP, 4><<<grid, 256, 0, s>>>(a); break;
-    case 8: k_fwd<R, COMP, 8><<<grid, 512, 0, s>>>(a); break;
-    case 16: k_fwd<R, COMP, 16><<<grid, 1024, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;
-  }
+  LDDMM_LAUNCH_WD(p.W, a.dim, grid, s, a, k_fwd, R, COMP)
   if (ev) (void)hipEventRecord(ev[1], s);
   switch (p.S) {
     case 1: break;
@@ -772,14 +791,7 @@ template <typename R, bool COMP>
 hipError_t adj_dispatch(const Plan& p, const AdjArgs& a, hipStream_t s, hipEvent_t* ev) {
   const dim3 grid(p.nb * p.S);
   if (ev) (void)hipEventRecord(ev[0], s);
-  switch (p.W) {
-    case 1: k_adj<R, COMP, 1><<<grid, 64, 0, s>>>(a); break;
-    case 2: k_adj<R, COMP, 2><<<grid, 128, 0, s>>>(a); break;
-    case 4: k_adj<R, COMP, 4><<<grid, 256, 0, s>>>(a); break;
-    case 8: k_adj<R, COMP, 8><<<grid, 512, 0, s>>>(a); break;
-    case 16: k_adj<R, COMP, 16><<<grid, 1024, 0, s>>>(a); break;
-    default: return hipErrorInvalidValue;
-  }
+  LDDMM_LAUNCH_WD(p.W, a.dim, grid, s, a, k_adj, R, COMP)
   if (ev) (void)hipEventRecord(ev[1], s);
   switch (p.S) {
     case 1: break;

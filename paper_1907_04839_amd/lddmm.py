@@ -28,7 +28,8 @@ _vp = ctypes.c_void_p
 class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("T", ctypes.c_int32), ("sigma", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("ckpt_every", ctypes.c_int32), ("energy", ctypes.c_int32)]
+                ("ckpt_every", ctypes.c_int32), ("energy", ctypes.c_int32),
+                ("dim", ctypes.c_int32)]
 
 
 class Timing(ctypes.Structure):
@@ -144,10 +145,10 @@ ENERGIES = {"initial": 0, "final": 1}
 
 
 def make_params(n: int, T: int, sigma: float, lam: float, precision="fp32c",
-                ckpt_every: int = 0, energy="initial") -> Params:
+                ckpt_every: int = 0, energy="initial", dim: int = 3) -> Params:
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     en = ENERGIES[energy] if isinstance(energy, str) else int(energy)
-    return Params(int(n), int(T), float(sigma), float(lam), prec, int(ckpt_every), en)
+    return Params(int(n), int(T), float(sigma), float(lam), prec, int(ckpt_every), en, int(dim))
 
 
 def solve_opts(precision="fp32c", **overrides) -> SolveOpts:
@@ -224,10 +225,10 @@ class Context:
 
     # -- calls -------------------------------------------------------------
     def shoot_forward(self, q0: torch.Tensor, p0: torch.Tensor, T: int, sigma: float,
-                      precision="fp32c", stream=None):
+                      precision="fp32c", stream=None, dim: int = 3):
         """Forward Euler flow (Alg. 1 forward loop).  Returns (q1, p1, H0)."""
         n = q0.shape[0]
-        prm = make_params(n, T, sigma, 0.0, precision)
+        prm = make_params(n, T, sigma, 0.0, precision, dim=dim)
         q1 = torch.empty_like(q0)
         p1 = torch.empty_like(q0)
         H0 = torch.empty((), dtype=torch.float64, device=q0.device)
@@ -237,10 +238,11 @@ class Context:
         return q1, p1, H0
 
     def velocity(self, q: torch.Tensor, p: torch.Tensor, x: torch.Tensor, sigma: float,
-                 precision="fp32c", stream=None, out: torch.Tensor | None = None) -> torch.Tensor:
+                 precision="fp32c", stream=None, out: torch.Tensor | None = None,
+                 dim: int = 3) -> torch.Tensor:
         """Velocity field of eq. 4 at the points x [M,3] for the landmark state (q, p)."""
         n, m = q.shape[0], x.shape[0]
-        prm = make_params(n, 1, sigma, 0.0, precision)
+        prm = make_params(n, 1, sigma, 0.0, precision, dim=dim)
         v = torch.empty_like(x) if out is None else out
         _check(lib().lddmm_velocity(self._h, ctypes.byref(prm), _pts(q, "q", n), _pts(p, "p", n),
                                     m, _pts(x, "x", m), _pts(v, "v", m), _stream(stream)),
@@ -249,13 +251,13 @@ class Context:
 
     def flow(self, q0: torch.Tensor, p0: torch.Tensor, x0: torch.Tensor, T: int, sigma: float,
              precision="fp32c", ckpt_every: int = 0, want_landmarks: bool = False, stream=None,
-             out: torch.Tensor | None = None):
+             out: torch.Tensor | None = None, dim: int = 3):
         """Points x0 [M,3] carried along the landmark motion from (q0, p0) (eq. 4).
 
         Returns x1, or (x1, q1, p1) with ``want_landmarks``.  ``out`` may be x0
         itself (in place)."""
         n, m = q0.shape[0], x0.shape[0]
-        prm = make_params(n, T, sigma, 0.0, precision, ckpt_every)
+        prm = make_params(n, T, sigma, 0.0, precision, ckpt_every, dim=dim)
         x1 = torch.empty_like(x0) if out is None else out
         q1 = torch.empty_like(q0) if want_landmarks else None
         p1 = torch.empty_like(q0) if want_landmarks else None
@@ -270,14 +272,14 @@ class Context:
                    sigma: float, lam: float, precision="fp32c", ckpt_every: int = 0,
                    want_q1: bool = True, stream=None, out: dict | None = None,
                    want_grad_q0: bool = False, want_grad_x: bool = False,
-                   energy="initial") -> GradResult:
+                   energy="initial", dim: int = 3) -> GradResult:
         """Loss of eq. 3 and its gradient w.r.t. p0 (Alg. 1 ComputeGradient);
         optionally also w.r.t. q0 and the target (lddmm_shoot_grad_all).
 
         ``out`` may hold preallocated ``grad`` [N,3], ``out3`` [3] and ``q1``.
         """
         n = q0.shape[0]
-        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy)
+        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy, dim)
         out = out or {}
         grad = out.get("grad")
         if grad is None:
@@ -307,13 +309,14 @@ class Context:
 
     def solve(self, q0: torch.Tensor, target: torch.Tensor, T: int, sigma: float, lam: float,
               precision="fp32c", p0: torch.Tensor | None = None, ckpt_every: int = 0,
-              want_trace: bool = False, stream=None, energy="initial", **opts) -> dict:
+              want_trace: bool = False, stream=None, energy="initial", dim: int = 3,
+              **opts) -> dict:
         """L-BFGS registration on the GPU (Alg. 1).  ``opts`` override the
         library defaults (max_iter, m, max_fev, gtol, ftol_rel, c1, c2, init);
         passing ``p0`` selects init = 2 (start from it)."""
         import numpy as np
         n = q0.shape[0]
-        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy)
+        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy, dim)
         if p0 is not None:
             opts.setdefault("init", 2)
         o = solve_opts(precision, **opts)

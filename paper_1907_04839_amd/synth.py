@@ -228,3 +228,31 @@ def ellipsoid_grid(k: int = 64, n: int = 4096, T: int = 40) -> tuple[Problem, np
     pts = grid(pb.q0.min(0) - pad, pb.q0.max(0) + pad, k)
     pb.name = f"ellipsoid{n}_T{T}_grid{k}"
     return pb, pts
+
+
+# --------------------------------------------------------------------------
+# planar problems (every z component 0)
+# --------------------------------------------------------------------------
+
+def planar(pb: Problem) -> Problem:
+    """The same problem with the z components of q0, target and p0 set to 0."""
+    z = lambda a: _c(np.concatenate([a[:, :2], np.zeros((a.shape[0], 1))], axis=1))  # noqa: E731
+    return Problem(pb.name + "_planar", z(pb.q0), z(pb.target), z(pb.p0), pb.sigma, pb.lam,
+                   pb.T, iters=pb.iters, precision=pb.precision, ckpt_every=pb.ckpt_every,
+                   seed=pb.seed)
+
+
+def ellipse_warp(seed: int = 1006, n: int = 4096, T: int = 40, iters: int = 200) -> Problem:
+    """Planar counterpart of ``ellipsoid_warp``: a noisy ellipse (semi-axes 60,
+    40, in-plane noise sd 1) in the plane z = 0, matched to its RK4 warp by 8
+    in-plane bumps (width 25, amplitude sd 6); sigma 8, lambda 1, p0 = 0."""
+    rng = np.random.default_rng(seed)
+    t = rng.uniform(0.0, 2.0 * math.pi, size=n)
+    q0 = np.stack([60.0 * np.cos(t), 40.0 * np.sin(t), np.zeros(n)], axis=1)
+    q0[:, :2] += rng.standard_normal((n, 2))
+    b = bumps(rng, 8, 25.0, 6.0, q0)
+    b.centres[:, 2] = 0.0
+    b.amps[:, 2] = 0.0
+    x = warp(q0, b)
+    return Problem(f"ellipse{n}_T{T}", _c(q0), _c(x), np.zeros_like(q0), 8.0, 1.0, T,
+                   iters=iters, precision="fp32c", seed=seed)

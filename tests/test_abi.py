@@ -57,7 +57,8 @@ def test_workspace_size_validation_on_host(lib):
            lddmm.make_params(10, 10, 1.0, -1.0), lddmm.make_params(10, 10, float("nan"), 1.0),
            lddmm.make_params(10, 10, 1.0, 1.0, precision=7),
            lddmm.make_params(10, 10, 1.0, 1.0, ckpt_every=-2),
-           lddmm.make_params(10, 10, 1.0, 1.0, energy=2)]
+           lddmm.make_params(10, 10, 1.0, 1.0, energy=2),
+           lddmm.make_params(10, 10, 1.0, 1.0, dim=1), lddmm.make_params(10, 10, 1.0, 1.0, dim=4)]
     for b in bad:
         with pytest.raises(lddmm.LddmmError) as e:
             lddmm.workspace_size(b)
