@@ -352,3 +352,60 @@ def test_server_rejects_final_energy():
                                               pb.q0.ctypes.data, pb.target.ctypes.data, None,
                                               ctypes.byref(jid))
         assert st == lddmm.EINVAL
+
+
+# ----------------------------------------------------------------- degenerate kernel widths, lambda = 0
+
+@pytest.mark.parametrize("mode", MODES)
+def test_tiny_sigma_decouples_every_landmark(gpu_ctx, mode):
+    """sigma far below the spacing: every off-diagonal kernel value underflows to 0,
+    each landmark moves alone in a straight line, q(1) = q0 + p0, and the gradient
+    is the single-landmark closed form p0 + 2 lambda (q0 + p0 - x)."""
+    import torch
+    rng = np.random.default_rng(1300)
+    n, T, lam = 3001, 7, 1.7
+    q0 = 10.0 * rng.standard_normal((n, 3))
+    p0 = 0.3 * rng.standard_normal((n, 3))
+    x = q0 + 0.5 * rng.standard_normal((n, 3))
+    r = gpu_ctx.shoot_grad(to_dev(q0), to_dev(p0), to_dev(x), T, 1e-3, lam, precision=mode)
+    torch.cuda.synchronize()
+    q1 = q0 + p0
+    g = p0 + 2.0 * lam * (q1 - x)
+    eq, eg = rel_err(host(r.q1) - q0, p0), rel_err(host(r.grad), g)
+    print(f"[tiny sigma {mode}] q1 {eq:.2e} grad {eg:.2e}", flush=True)
+    tol = 1e-13 if mode == "fp64" else 2e-7    # FP32 records hold p and a rounded to FP32
+    assert eq < tol and eg < tol
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_huge_sigma_translates_the_cloud_rigidly(gpu_ctx, mode):
+    """sigma far above the cloud: every kernel value is 1 (to 1e-12), Hp_i is the
+    total momentum P and Hq vanishes, so every landmark moves by P."""
+    import torch
+    rng = np.random.default_rng(1301)
+    n, T = 2000, 5
+    q0 = rng.standard_normal((n, 3))
+    p0 = 1e-3 * rng.standard_normal((n, 3))
+    q1, p1, _ = gpu_ctx.shoot_forward(to_dev(q0), to_dev(p0), T, 1e6, precision=mode)
+    torch.cuda.synchronize()
+    P = p0.sum(0)
+    e = np.abs(host(q1) - q0 - P[None, :]).max() / np.abs(P).max()
+    print(f"[huge sigma {mode}] displacement error {e:.2e}", flush=True)
+    assert e < (1e-9 if mode == "fp64" else 1e-5)
+    np.testing.assert_allclose(host(p1), p0, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_zero_lambda_gradient_is_Hp0(gpu_ctx, orc_mt, mode):
+    """lambda = 0: the terminal adjoint is 0 and stays 0, so dL/dp0 = Hp(q0, p0) and
+    the loss is H(q0, p0)."""
+    import torch
+    pb = synth.random_problem(1302, 1500, T=4)
+    r = gpu_ctx.shoot_grad(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), 4, pb.sigma, 0.0,
+                           precision=mode)
+    torch.cuda.synchronize()
+    _, Hp = orc_mt.pair_forward(pb.q0, pb.p0, pb.sigma)
+    H = orc_mt.hamiltonian(pb.q0, pb.p0, pb.sigma)
+    eg = rel_err(host(r.grad), Hp)
+    assert eg < TOL[mode] and abs(r.loss.item() - H) < TOL[mode] * H
+    assert r.loss.item() == r.H0.item()
