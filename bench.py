@@ -226,8 +226,15 @@ def cpu_baseline(pb, target_s=12.0, budget_s=25.0):
     for _ in range(evals):
         oracle.shoot_grad(pb.q0, p0, pb.target, pb.sigma, pb.lam, T)
     dt = time.perf_counter() - t0
+    # one thread, on a 2-step sample, for the paper's single-CPU framing
+    oracle.set_threads(1)
+    t1 = time.perf_counter()
+    oracle.shoot_grad(pb.q0, p0, pb.target, pb.sigma, pb.lam, 2)
+    one = 2 * 2 * pb.n ** 2 / (time.perf_counter() - t1)
+    oracle.set_threads(threads)
     return {"value": evals * 2 * T * pb.n ** 2 / dt, "unit": "pair-interactions/s",
             "cores": threads, "kind": "oracle", "seconds": round(dt, 2),
+            "value_1_thread": round(one, 1),
             "sample": f"{evals} FP64 loss+gradient evaluations of the same N={pb.n} problem "
                       f"with T={T} Euler steps ({evals * 2 * T * pb.n ** 2:.3g} pairs)"}
 

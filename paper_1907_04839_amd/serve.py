@@ -100,11 +100,14 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=100)
     ap.add_argument("--mode", choices=["batched", "sequential", "both"], default="both")
     ap.add_argument("--max-slots", type=int, default=32)
+    ap.add_argument("--hbm-budget-mb", type=int, default=1024,
+                    help="the server's arena: jobs wait until their footprint fits")
     a = ap.parse_args(argv)
     jobs, arrivals = make_stream(a.jobs, a.rate, a.iters)
     out = {}
     if a.mode in ("batched", "both"):
-        r = run_batched(jobs, arrivals, max_slots=a.max_slots)
+        r = run_batched(jobs, arrivals, max_slots=a.max_slots,
+                        hbm_budget_bytes=a.hbm_budget_mb << 20)
         r.pop("results")
         out["batched"] = r
         print("batched", json.dumps(r), flush=True)
