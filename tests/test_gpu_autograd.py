@@ -131,3 +131,32 @@ def test_template_and_target_gradients_through_autograd(orc_mt):
     # translation identity on the device result
     tot = (q0.grad.sum(0) + x.grad.sum(0)).abs().max().item()
     assert tot < 1e-10 * q0.grad.abs().sum().item()
+
+
+def test_sphere16384_directional_derivatives_match_fp64_differences(gpu_ctx):
+    """The full 16384-landmark sphere workload (T = 100, checkpoints every 10): for
+    seeded random unit directions d, central differences of the FP64 loss (eps 1e-4)
+    agree with g . d from the FP64 gradient and, to FP32 accuracy, from the
+    compensated FP32 gradient."""
+    import torch
+    pb = synth.sphere_autograd()
+    q0, x, p0 = to_dev(pb.q0), to_dev(pb.target), to_dev(pb.p0)
+    ev = lambda p, mode: gpu_ctx.shoot_grad(q0, p, x, pb.T, pb.sigma, pb.lam,  # noqa: E731
+                                            precision=mode, ckpt_every=10, want_q1=False)
+    g64, g32 = ev(p0, "fp64").grad.clone(), ev(p0, "fp32c").grad.clone()
+    rng = np.random.default_rng(1400)
+    eps = 1e-4
+    worst = {"fp64": 0.0, "fp32c": 0.0}
+    for _ in range(8):
+        d = rng.standard_normal(pb.p0.shape)
+        d = to_dev(d / np.linalg.norm(d))
+        lp = ev(p0 + eps * d, "fp64").loss.item()
+        lm = ev(p0 - eps * d, "fp64").loss.item()
+        fd = (lp - lm) / (2 * eps)
+        for mode, g in (("fp64", g64), ("fp32c", g32)):
+            gd = float((g * d).sum())
+            worst[mode] = max(worst[mode], abs(gd - fd) / abs(fd))
+    torch.cuda.synchronize()
+    print(f"[sphere16384 directional FD] fp64 {worst['fp64']:.2e} fp32c {worst['fp32c']:.2e}",
+          flush=True)
+    assert worst["fp64"] < 1e-6 and worst["fp32c"] < 1e-4
