@@ -12,6 +12,12 @@
  *   gradient     dL/dp0 by the exact adjoint of the discrete Euler map,
  *                run backwards in time                                (Alg. 1)
  *   solver       L-BFGS over p0                                       (Sec. 2.1; Alg. 1)
+ *   velocity     v(x,t) = sum_l g(|q_l(t) - x|) p_l(t) at any points x, and
+ *                the flow of points carried by the landmark motion    (eq. 4)
+ *
+ * Options per call (lddmm_params): the precision of the pair sums, trajectory
+ * checkpointing, the energy term taken at t = 1 instead of t = 0 (the loss as
+ * Alg. 1 evaluates it) and a planar specialisation (Sec. 2.5).
  *
  * Conventions shared by every call:
  *   - Point sets (q0, p0, target, q1, p1, grad) are DEVICE pointers to [n][3]
