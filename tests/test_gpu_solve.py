@@ -112,3 +112,16 @@ def test_invalid_solver_options(gpu_ctx):
         with pytest.raises(lddmm.LddmmError) as e:
             gpu_ctx.solve(to_dev(pb.q0), to_dev(pb.target), 2, 1.0, 1.0, "fp64", **bad)
         assert e.value.status == lddmm.EINVAL
+
+
+def test_checkpointed_solve_is_bitwise_identical(gpu_ctx):
+    """The solver on a checkpointed trajectory (every 3 of 10 steps kept)
+    takes the same iterates as on the whole trajectory."""
+    import torch
+    pb = synth.random_problem(404, 900, T=10)
+    q0, x = to_dev(pb.q0), to_dev(pb.target)
+    a = gpu_ctx.solve(q0, x, 10, pb.sigma, pb.lam, "fp32c", max_iter=12)
+    b = gpu_ctx.solve(q0, x, 10, pb.sigma, pb.lam, "fp32c", ckpt_every=3, max_iter=12)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(a["p0"].cpu().numpy(), b["p0"].cpu().numpy())
+    assert a["loss"] == b["loss"] and a["iters"] == b["iters"] and a["fevals"] == b["fevals"]
