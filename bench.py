@@ -319,7 +319,7 @@ def serving(n_jobs: int, rate: float = 200.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ellipsoid4096")
     ap.add_argument("--precision", default="fp32c", choices=["fp32", "fp32c", "fp64"])
