@@ -77,3 +77,32 @@ def test_binding_has_no_cpu_fallback():
     """The product path must not reach the oracle."""
     src = open(os.path.join(ROOT, "paper_1907_04839_amd", "lddmm.py")).read()
     assert "oracle" not in src.replace("no CPU fallback", "")
+
+
+def test_calls_without_a_context_are_rejected_on_the_host(lib):
+    """Every compute entry point validates its arguments before touching the
+    device: with no context it returns EINVAL and sets a detail string."""
+    from paper_1907_04839_amd import lddmm
+    L = lddmm.lib()
+    prm = lddmm.make_params(16, 4, 1.0, 1.0)
+    P = ctypes.byref(prm)
+    fake = ctypes.c_void_p(0x1000)            # never dereferenced: the call fails first
+    calls = {
+        "lddmm_shoot_forward": lambda: L.lddmm_shoot_forward(None, P, fake, fake, None, None,
+                                                             None, None),
+        "lddmm_shoot_grad": lambda: L.lddmm_shoot_grad(None, P, fake, fake, fake, fake, fake,
+                                                       None, None),
+        "lddmm_shoot_grad_all": lambda: L.lddmm_shoot_grad_all(None, P, fake, fake, fake, fake,
+                                                               fake, None, None, None, None),
+        "lddmm_velocity": lambda: L.lddmm_velocity(None, P, fake, fake, 5, fake, fake, None),
+        "lddmm_flow": lambda: L.lddmm_flow(None, P, fake, fake, 5, fake, fake, None, None, None),
+    }
+    for name, call in calls.items():
+        assert call() == lddmm.EINVAL, name
+        assert L.lddmm_last_error(None), name
+    o = lddmm.solve_opts("fp32c")
+    assert L.lddmm_solve(None, P, ctypes.byref(o), fake, fake, fake, None, None,
+                         None) == lddmm.EINVAL
+    bad = lddmm.make_params(16, 4, 1.0, 1.0, dim=5)
+    assert L.lddmm_velocity(None, ctypes.byref(bad), fake, fake, 5, fake, fake,
+                            None) == lddmm.EINVAL
