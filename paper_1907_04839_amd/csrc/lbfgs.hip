@@ -40,14 +40,14 @@ __device__ __forceinline__ double block_dot(const double* __restrict__ a,
                                             const double* __restrict__ b, int m, double* red) {
   double s = 0.0;
   for (int k = threadIdx.x; k < m; k += kThreads) s += a[k] * b[k];
-  red[threadIdx.x] = s;
+  // butterfly within the wave (lane 0's total is used), then the waves' totals
+  // in wave order: a fixed order, two barriers per dot product
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-    __syncthreads();
-  }
-  const double r = red[0];
-  __syncthreads();
+  double r = red[0];
+  for (int w = 1; w < kThreads / 64; ++w) r += red[w];
+  __syncthreads();   // red is reused by the next reduction
   return r;
 }
 
