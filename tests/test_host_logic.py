@@ -40,3 +40,30 @@ def test_auto_checkpoint_choice():
     s = ShootConfig(100, 6.0, 1.0, "fp32c", "auto", 8 << 20).resolve_ckpt(16384)
     assert 1 <= s <= 10 and (s + 1) * 16384 * 32 <= 8 << 20
     assert ShootConfig(100, 6.0, 1.0, "fp32c", 7).resolve_ckpt(16384) == 7
+
+
+def test_fp64_exp2_table_matches_its_generator_and_is_accurate():
+    """The pair kernels' FP64 2^f polynomial: the table in the kernel source is the
+    generator's output, and the polynomial meets 2^f within one ulp on [-1/2, 1/2]
+    (reference values in 40-digit decimal arithmetic)."""
+    import importlib.util
+    import random
+    from decimal import Decimal, getcontext
+    path = os.path.join(ROOT, "paper_1907_04839_amd", "csrc", "gen_exp2.py")
+    spec = importlib.util.spec_from_file_location("gen_exp2", path)
+    gen = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(gen)
+    coef = gen.coefficients()
+    src = open(os.path.join(ROOT, "paper_1907_04839_amd", "csrc", "shoot_kernels.hip")).read()
+    assert gen.cpp_table(coef) in src
+    getcontext().prec = 40
+    ln2 = Decimal(2).ln()
+    rng = random.Random(5)
+    worst = 0.0
+    for f in [-0.5 + k / 2000 for k in range(2001)] + [rng.uniform(-0.5, 0.5) for _ in range(2000)]:
+        p = coef[-1]
+        for c in reversed(coef[:-1]):
+            p = p * f + c
+        exact = (Decimal(f) * ln2).exp()
+        worst = max(worst, float(abs((Decimal(p) - exact) / exact)))
+    assert worst < 2.3e-16, worst
