@@ -36,12 +36,10 @@ constexpr int kThreads = 1024;
 
 enum Phase : int { kInit = 0, kBracket = 1, kZoom = 2 };
 
-__device__ __forceinline__ double block_dot(const double* __restrict__ a,
-                                            const double* __restrict__ b, int m, double* red) {
-  double s = 0.0;
-  for (int k = threadIdx.x; k < m; k += kThreads) s += a[k] * b[k];
-  // butterfly within the wave (lane 0's total is used), then the waves' totals
-  // in wave order: a fixed order, two barriers per dot product
+// Block-wide sums of per-thread partials in a fixed order: a butterfly within
+// each wave (lane 0's total is used), then the waves' totals in wave order.
+// Two barriers per call.
+__device__ __forceinline__ double block_sum(double s, double* red) {
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
@@ -49,6 +47,38 @@ __device__ __forceinline__ double block_dot(const double* __restrict__ a,
   for (int w = 1; w < kThreads / 64; ++w) r += red[w];
   __syncthreads();   // red is reused by the next reduction
   return r;
+}
+
+// Two sums in one pass of barriers; each is summed exactly as block_sum would.
+__device__ __forceinline__ void block_sum2(double s, double t, double* red, double* rs,
+                                           double* rt) {
+  constexpr int NW = kThreads / 64;
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_xor(s, off, 64);
+    t += __shfl_xor(t, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = s;
+    red[NW + (threadIdx.x >> 6)] = t;
+  }
+  __syncthreads();
+  double a = red[0], b = red[NW];
+  for (int w = 1; w < NW; ++w) {
+    a += red[w];
+    b += red[NW + w];
+  }
+  __syncthreads();
+  *rs = a;
+  *rt = b;
+}
+
+// Each thread owns elements k = threadIdx.x + j kThreads of every vector and
+// sums its products in increasing k, so fusing passes below changes no bit.
+__device__ __forceinline__ double block_dot(const double* __restrict__ a,
+                                            const double* __restrict__ b, int m, double* red) {
+  double s = 0.0;
+  for (int k = threadIdx.x; k < m; k += kThreads) s += a[k] * b[k];
+  return block_sum(s, red);
 }
 
 // x_t = x + a d without FMA contraction (the same rounding as x + a*d on a host)
@@ -85,46 +115,89 @@ __device__ __forceinline__ void snapshot(const LbfgsBufs& B) {
 // state, read by all threads and written by thread 0 only, between barriers.
 __device__ void new_direction(const LbfgsBufs& B, const LbfgsOpts& o, LbfgsState& st,
                               double* red) {
+  // Two-loop recursion (Nocedal & Wright, Alg. 7.4).  Every thread updates
+  // only its own elements of d, so each update is fused with the inner
+  // product the next step needs: one vector pass per history entry instead of
+  // two, the same arithmetic in the same order.
   const int m3 = B.m3, M = o.m;
   const int used = st.used, newest = st.newest;
-  for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] = B.g[k];
-  __syncthreads();
-  for (int h = 0; h < used; ++h) {             // newest to oldest
-    const int s = (newest - h + M) % M;
-    const double* Ss = B.S + (size_t)s * m3;
-    const double* Ys = B.Y + (size_t)s * m3;
-    const double al = st.rho[s] * block_dot(Ss, B.d, m3, red);
-    if (threadIdx.x == 0) st.alpha[s] = al;
-    for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] -= al * Ys[k];
-    __syncthreads();
+  const auto slot = [&](int h) { return (newest - h + M) % M; };   // h = 0: newest
+  const auto Sv = [&](int h) { return B.S + (size_t)slot(h) * m3; };
+  const auto Yv = [&](int h) { return B.Y + (size_t)slot(h) * m3; };
+  double gd, dd = 0.0;
+  if (used == 0) {                               // steepest descent: d = -g
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < m3; k += kThreads) {
+      const double v = -B.g[k];
+      B.d[k] = v;
+      a += B.g[k] * v;
+      b += v * v;
+    }
+    block_sum2(a, b, red, &gd, &dd);
+  } else {
+    double sy, yy;                               // H0 scaling from the newest pair
+    {
+      const double* Sn = Sv(0);
+      const double* Yn = Yv(0);
+      double a = 0.0, b = 0.0;
+      for (int k = threadIdx.x; k < m3; k += kThreads) {
+        a += Sn[k] * Yn[k];
+        b += Yn[k] * Yn[k];
+      }
+      block_sum2(a, b, red, &sy, &yy);
+    }
+    const double gamma = sy / yy;
+    double acc = 0.0;                            // d = g, and S_0 . d
+    {
+      const double* S0 = Sv(0);
+      for (int k = threadIdx.x; k < m3; k += kThreads) {
+        const double v = B.g[k];
+        B.d[k] = v;
+        acc += S0[k] * v;
+      }
+    }
+    for (int h = 0; h < used; ++h) {             // newest to oldest
+      const double al = st.rho[slot(h)] * block_sum(acc, red);
+      if (threadIdx.x == 0) st.alpha[slot(h)] = al;
+      const double* Ys = Yv(h);
+      const bool last = h + 1 == used;
+      const double* Nx = last ? Yv(used - 1) : Sv(h + 1);   // the next inner product's vector
+      acc = 0.0;
+      for (int k = threadIdx.x; k < m3; k += kThreads) {
+        double v = B.d[k] - al * Ys[k];
+        if (last) v *= gamma;
+        B.d[k] = v;
+        acc += Nx[k] * v;
+      }
+    }
+    for (int h = used - 1; h >= 0; --h) {         // oldest to newest
+      const double beta = st.rho[slot(h)] * block_sum(acc, red);
+      const double al = st.alpha[slot(h)];
+      const double* Ss = Sv(h);
+      const bool last = h == 0;
+      const double* Nx = last ? B.g : Yv(h - 1);
+      acc = 0.0;
+      for (int k = threadIdx.x; k < m3; k += kThreads) {
+        double v = B.d[k] + (al - beta) * Ss[k];
+        if (last) v = -v;                        // the direction is -H g
+        B.d[k] = v;
+        acc += Nx[k] * v;
+      }
+    }
+    gd = block_sum(acc, red);
   }
-  if (used > 0) {
-    const double* Sn = B.S + (size_t)newest * m3;
-    const double* Yn = B.Y + (size_t)newest * m3;
-    const double gamma = block_dot(Sn, Yn, m3, red) / block_dot(Yn, Yn, m3, red);
-    for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] *= gamma;
-    __syncthreads();
-  }
-  for (int h = used - 1; h >= 0; --h) {         // oldest to newest
-    const int s = (newest - h + M) % M;
-    const double* Ss = B.S + (size_t)s * m3;
-    const double* Ys = B.Y + (size_t)s * m3;
-    const double beta = st.rho[s] * block_dot(Ys, B.d, m3, red);
-    const double al = st.alpha[s];
-    for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] += (al - beta) * Ss[k];
-    __syncthreads();
-  }
-  for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] = -B.d[k];
-  __syncthreads();
-  double gd = block_dot(B.g, B.d, m3, red);
   const bool restart = !(gd < 0.0);             // not a descent direction: restart
   if (restart) {
-    for (int k = threadIdx.x; k < m3; k += kThreads) B.d[k] = -B.g[k];
-    __syncthreads();
-    gd = block_dot(B.g, B.d, m3, red);
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < m3; k += kThreads) {
+      const double v = -B.g[k];
+      B.d[k] = v;
+      a += B.g[k] * v;
+      b += v * v;
+    }
+    block_sum2(a, b, red, &gd, &dd);
   }
-  const double a0 =
-      (restart || used == 0) ? 1.0 / sqrt(block_dot(B.d, B.d, m3, red)) : 1.0;
+  const double a0 = (restart || used == 0) ? 1.0 / sqrt(dd) : 1.0;
   if (threadIdx.x == 0) {
     if (restart) { st.used = 0; st.newest = -1; }
     st.d0 = gd;
@@ -148,21 +221,26 @@ __device__ void accept(const LbfgsBufs& B, const LbfgsOpts& o, LbfgsState& st, d
   const double f_old = st.f;
   double* Ss = B.S + (size_t)slot * m3;
   double* Ys = B.Y + (size_t)slot * m3;
-  for (int k = threadIdx.x; k < m3; k += kThreads) {
-    Ss[k] = B.xt[k] - B.x[k];
-    Ys[k] = B.gt[k] - B.g[k];
-  }
-  __syncthreads();
-  const double sy = block_dot(Ss, Ys, m3, red);
-  const double yy = block_dot(Ys, Ys, m3, red);
-  for (int k = threadIdx.x; k < m3; k += kThreads) {
-    B.x[k] = B.xt[k];
-    B.g[k] = B.gt[k];
+  double a = 0.0, b = 0.0, gg = 0.0, xx = 0.0;
+  for (int k = threadIdx.x; k < m3; k += kThreads) {   // new pair, and x, g move to x_t, g_t
+    const double sv = B.xt[k] - B.x[k];
+    const double yv = B.gt[k] - B.g[k];
+    Ss[k] = sv;
+    Ys[k] = yv;
+    a += sv * yv;
+    b += yv * yv;
+    const double xv = B.xt[k], gv = B.gt[k];
+    B.x[k] = xv;
+    B.g[k] = gv;
+    gg += gv * gv;
+    xx += xv * xv;
   }
   snapshot(B);
-  __syncthreads();
-  const double gnorm = sqrt(block_dot(B.g, B.g, m3, red));
-  const double xnorm = sqrt(block_dot(B.x, B.x, m3, red));
+  double sy, yy, gsq, xsq;
+  block_sum2(a, b, red, &sy, &yy);
+  block_sum2(gg, xx, red, &gsq, &xsq);
+  const double gnorm = sqrt(gsq);
+  const double xnorm = sqrt(xsq);
   if (threadIdx.x == 0) {
     if (sy > 1e-16 * yy && sy > 0.0) {
       st.rho[slot] = 1.0 / sy;
