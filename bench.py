@@ -90,6 +90,25 @@ def time_steps(ctx, dev, pb, precision, steps, warmup, ckpt_every=0, dim=3):
     return dt, float(out["out3"][0])
 
 
+def step_event_times(ctx, dev, pb, precision, steps):
+    """Each evaluation bracketed by its own pair of events on the launch stream:
+    per-step median and minimum in ms."""
+    import statistics
+    import torch
+    q0, x, p0 = dev["q0"], dev["x"], dev["p0"]
+    out = dict(grad=torch.empty_like(q0), out3=torch.empty(3, dtype=torch.float64, device=q0.device))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for a, b in evs:
+        a.record()
+        ctx.shoot_grad(q0, p0, x, pb.T, pb.sigma, pb.lam, precision=precision, want_q1=False,
+                       out=out)
+        b.record()
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in evs]
+    return statistics.median(ms), min(ms)
+
+
 def kernel_times(ctx, dev, pb, precision, steps, ckpt_every=0, dim=3):
     """Average pair-kernel durations from HIP events recorded on the launch stream."""
     ctx.timing(reset=True)
@@ -362,6 +381,8 @@ def main():
         value = pairs_per_step * args.steps / dt
         log(f"[bench] {value:.4g} pair-interactions/s, {1e3 * dt / args.steps:.3f} ms/step, "
             f"loss {loss:.6g}")
+        med, mn = step_event_times(ctx, dev, pb, args.precision, args.steps)
+        log(f"[bench] per-step events: median {med:.3f} ms, min {mn:.3f} ms")
         kt = kernel_times(ctx, dev, pb, args.precision, args.steps)
         roof = roofline(pb.n, kt, measured_traffic(args.workload, args.precision), args.precision)
         log(f"[bench] kernels: fwd {kt['fwd_us']:.2f} us, adj {kt['adj_us']:.2f} us per launch; "
@@ -415,6 +436,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "ms_per_step_events": {"median": round(med, 4), "min": round(mn, 4)},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -1,6 +1,7 @@
 """Precision study on the 65536-landmark two-blob workload: one gradient in
 FP32 (one running sum per wave), FP32 compensated (64-pair tiles folded into
-FP64) and FP64, each against the FP64 oracle on the full problem.
+FP64) and FP64, each against the FP64 oracle on the full problem: loss, H0,
+q(1), the gradient, and the energy of the final state H(q(1), p(1)).
 
 The oracle's full-T evaluation costs ~4e11 pair terms (minutes on 16 host
 threads), so by default the study runs the full N with T = 5 Euler steps;
@@ -22,6 +23,7 @@ def test_precision_modes_against_oracle(gpu_ctx, orc_mt):
     pb = synth.two_blobs()
     T = int(os.environ.get("LDDMM_PRECISION_STUDY_T", "5"))
     o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, T)
+    of = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, T, energy="final")
     errs = {}
     for mode in ("fp32", "fp32c", "fp64"):
         r = gpu_ctx.shoot_grad(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), T, pb.sigma,
@@ -31,6 +33,11 @@ def test_precision_modes_against_oracle(gpu_ctx, orc_mt):
                           H0=abs(r.H0.item() - o["H0"]) / abs(o["H0"]),
                           q1=rel_err(r.q1.cpu().numpy(), o["q1"]),
                           grad=rel_err(r.grad.cpu().numpy(), o["grad"]))
+        # the energy at the final state, H(q(1), p(1)), through the loss option
+        rf = gpu_ctx.shoot_grad(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), T, pb.sigma,
+                                pb.lam, precision=mode, energy="final", want_q1=False)
+        torch.cuda.synchronize()
+        errs[mode]["HT"] = abs(rf.H0.item() - of["H0"]) / abs(of["H0"])
         print(f"[precision blobs65536 T={T} {mode}] " +
               " ".join(f"{k}={v:.2e}" for k, v in errs[mode].items()), flush=True)
     assert max(errs["fp64"].values()) <= 1e-12
