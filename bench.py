@@ -200,10 +200,18 @@ def traffic_probe(name: str, precision: str):
 
 
 def kernel_source_hash() -> str:
+    """SHA-256 (first 16 hex digits) of the pair-kernel source with its comments
+    and blank space removed: an edit to the code invalidates recorded counters,
+    an edit to a comment does not."""
     import hashlib
+    import re
     src = os.path.join(ROOT, "paper_1907_04839_amd", "csrc", "shoot_kernels.hip")
-    with open(src, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    with open(src, encoding="utf-8") as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
 
 
 def measured_traffic(name: str, precision: str):
