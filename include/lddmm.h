@@ -73,8 +73,8 @@ typedef enum {
 typedef enum { LDDMM_ENERGY_INITIAL = 0, LDDMM_ENERGY_FINAL = 1 } lddmm_energy;
 
 typedef struct {
-  int32_t n;               /* landmarks, >= 1 */
-  int32_t T;               /* Euler steps, >= 1 (dt = 1/T) */
+  int32_t n;               /* landmarks, 1..2^26 */
+  int32_t T;               /* Euler steps, 1..2^20 (dt = 1/T) */
   double sigma;            /* Gaussian kernel width (standard deviation), > 0 */
   double lambda;           /* mismatch weight, >= 0 */
   int32_t precision;       /* lddmm_precision */
@@ -191,8 +191,8 @@ typedef struct lddmm_server lddmm_server;
 typedef struct {
   int32_t device;
   int32_t max_slots;          /* jobs on the GPU at once, 1..1024 */
-  int32_t max_n;              /* largest n accepted */
-  int32_t T;                  /* Euler steps of every job */
+  int32_t max_n;              /* largest n accepted, 1..2^20 */
+  int32_t T;                  /* Euler steps of every job, 1..2^20 */
   int32_t precision;          /* lddmm_precision of every job */
   size_t hbm_budget_bytes;    /* arena for job state, allocated at create */
 } lddmm_server_config;
@@ -259,7 +259,7 @@ lddmm_status lddmm_shoot_grad_all(lddmm_ctx* ctx, const lddmm_params* params, co
  *   params : n, sigma and precision are used (T and ckpt_every are ignored;
  *            lambda must still be valid)
  *   q, p   : in, [n][3] device FP64, one landmark state (q(t), p(t))
- *   m      : number of points, >= 0 (0: nothing is launched)
+ *   m      : number of points, 0..2^30 (0: nothing is launched)
  *   x      : in, [m][3] device FP64 points
  *   v      : out, [m][3] device FP64 velocities
  * The pair sums run in the precision mode, as in the forward step; a
@@ -273,7 +273,7 @@ lddmm_status lddmm_velocity(lddmm_ctx* ctx, const lddmm_params* params, const do
  * Euler step moving a point by dt v(x, t) (eq. 4) with the landmark state of
  * the same step t, so that a point placed on a landmark follows it.
  *   q0, p0 : in, [n][3] device FP64
- *   m      : number of points, >= 0
+ *   m      : number of points, 0..2^30
  *   x0     : in, [m][3] device FP64 points at t = 0
  *   x1     : out, [m][3] device FP64 points at t = 1 (may be the same buffer
  *            as x0)

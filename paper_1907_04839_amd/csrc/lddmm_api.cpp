@@ -84,6 +84,13 @@ namespace {
 
 thread_local std::string g_err;   // errors that have no context
 
+// Size limits.  Landmark arrays are indexed with 32-bit ints in the kernels
+// (6 n fits), point arrays of the flow with 64-bit offsets; T + 1 trajectory
+// slots must not overflow either.
+constexpr int kMaxLandmarks = 1 << 26;
+constexpr int kMaxSteps = 1 << 20;
+constexpr int kMaxPoints = 1 << 30;
+
 // Waves the pair kernels aim to have in a launch (256 CUs x 4 SIMDs x 16,
 // queued as resources free up); LDDMM_TARGET_WAVES overrides it for tuning.
 int target_waves() {
@@ -121,8 +128,9 @@ lddmm_status hip_fail(lddmm_ctx* ctx, hipError_t e, const char* what) {
 lddmm_status check_params(lddmm_ctx* ctx, const lddmm_params* p) {
   if (!p) return fail(ctx, LDDMM_EINVAL, "params is NULL");
   if (p->n < 1) return fail(ctx, LDDMM_EINVAL, "n must be >= 1 (got %d)", p->n);
-  if (p->n > (1 << 26)) return fail(ctx, LDDMM_EINVAL, "n too large (%d)", p->n);
-  if (p->T < 1) return fail(ctx, LDDMM_EINVAL, "T must be >= 1 (got %d)", p->T);
+  if (p->n > kMaxLandmarks) return fail(ctx, LDDMM_EINVAL, "n too large (%d)", p->n);
+  if (p->T < 1 || p->T > kMaxSteps)
+    return fail(ctx, LDDMM_EINVAL, "T must be in 1..%d (got %d)", kMaxSteps, p->T);
   if (!(p->sigma > 0.0) || !std::isfinite(p->sigma))
     return fail(ctx, LDDMM_EINVAL, "sigma must be finite and > 0");
   if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda))
@@ -506,8 +514,10 @@ FlowArgs flow_args(const Job& j, int m, int W) {
 lddmm_status lddmm_velocity(lddmm_ctx* ctx, const lddmm_params* params, const double* q,
                             const double* p, int32_t m, const double* x, double* v,
                             void* stream) {
-  if (ctx && params && (!q || !p || m < 0 || (m > 0 && (!x || !v))))
-    return fail(ctx, LDDMM_EINVAL, "q and p must not be NULL, m >= 0, x and v non-NULL if m > 0");
+  if (m < 0 || m > kMaxPoints)
+    return fail(ctx, LDDMM_EINVAL, "m must be in 0..%d (got %d)", kMaxPoints, m);
+  if (ctx && params && (!q || !p || (m > 0 && (!x || !v))))
+    return fail(ctx, LDDMM_EINVAL, "q and p must not be NULL, x and v non-NULL if m > 0");
   if (!params) return fail(ctx, LDDMM_EINVAL, "params is NULL");
   lddmm_params one = *params;   // one state: no trajectory beyond slot 0
   one.T = 1;
@@ -534,9 +544,10 @@ lddmm_status lddmm_velocity(lddmm_ctx* ctx, const lddmm_params* params, const do
 lddmm_status lddmm_flow(lddmm_ctx* ctx, const lddmm_params* params, const double* q0,
                         const double* p0, int32_t m, const double* x0, double* x1, double* q1,
                         double* p1, void* stream) {
-  if (ctx && params && (!q0 || !p0 || m < 0 || (m > 0 && (!x0 || !x1))))
-    return fail(ctx, LDDMM_EINVAL,
-                "q0 and p0 must not be NULL, m >= 0, x0 and x1 non-NULL if m > 0");
+  if (m < 0 || m > kMaxPoints)
+    return fail(ctx, LDDMM_EINVAL, "m must be in 0..%d (got %d)", kMaxPoints, m);
+  if (ctx && params && (!q0 || !p0 || (m > 0 && (!x0 || !x1))))
+    return fail(ctx, LDDMM_EINVAL, "q0 and p0 must not be NULL, x0 and x1 non-NULL if m > 0");
   if (!params) return fail(ctx, LDDMM_EINVAL, "params is NULL");
   const bool seg = params->ckpt_every > 0 && params->ckpt_every < params->T;
   Job j;

@@ -449,7 +449,8 @@ extern "C" {
 
 lddmm_status lddmm_server_job_footprint(const lddmm_server_config* cfg, int32_t n, int32_t m,
                                         size_t* bytes) {
-  if (!cfg || !bytes || n < 1 || m < 1 || m > kMaxHistory || cfg->T < 1 ||
+  if (!cfg || !bytes || n < 1 || n > (1 << 26) || m < 1 || m > kMaxHistory || cfg->T < 1 ||
+      cfg->T > (1 << 20) ||
       cfg->precision < LDDMM_FP32 || cfg->precision > LDDMM_FP64)
     return sfail(nullptr, LDDMM_EINVAL, "invalid footprint query");
   *bytes = job_layout(n, cfg->T, cfg->precision, m).total;
@@ -460,7 +461,8 @@ lddmm_status lddmm_server_create(const lddmm_server_config* cfg, lddmm_server** 
   if (!cfg || !out) return sfail(nullptr, LDDMM_EINVAL, "cfg and out must not be NULL");
   *out = nullptr;
   if (cfg->max_slots < 1 || cfg->max_slots > 1024 || cfg->max_n < 1 || cfg->max_n > (1 << 20) ||
-      cfg->T < 1 || cfg->precision < LDDMM_FP32 || cfg->precision > LDDMM_FP64 ||
+      cfg->T < 1 || cfg->T > (1 << 20) || cfg->precision < LDDMM_FP32 ||
+      cfg->precision > LDDMM_FP64 ||
       cfg->hbm_budget_bytes < 4096)
     return sfail(nullptr, LDDMM_EINVAL, "invalid server configuration");
   int count = 0;

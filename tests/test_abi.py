@@ -106,3 +106,28 @@ def test_calls_without_a_context_are_rejected_on_the_host(lib):
     bad = lddmm.make_params(16, 4, 1.0, 1.0, dim=5)
     assert L.lddmm_velocity(None, ctypes.byref(bad), fake, fake, 5, fake, fake,
                             None) == lddmm.EINVAL
+
+
+def test_size_limits_are_rejected_on_the_host(lib):
+    """n, T and the point count m have upper limits that keep every offset the
+    kernels form in range; larger values are EINVAL before anything else."""
+    from paper_1907_04839_amd import lddmm
+    L = lddmm.lib()
+    assert lddmm.workspace_size(lddmm.make_params(1 << 26, 1, 1.0, 1.0)) > 0
+    assert lddmm.workspace_size(lddmm.make_params(16, 1 << 20, 1.0, 1.0, ckpt_every=1024)) > 0
+    for b in (lddmm.make_params((1 << 26) + 1, 4, 1.0, 1.0),
+              lddmm.make_params(16, (1 << 20) + 1, 1.0, 1.0),
+              lddmm.make_params(16, 2 ** 31 - 1, 1.0, 1.0)):
+        with pytest.raises(lddmm.LddmmError) as e:
+            lddmm.workspace_size(b)
+        assert e.value.status == lddmm.EINVAL
+    prm = lddmm.make_params(16, 4, 1.0, 1.0)
+    P = ctypes.byref(prm)
+    fake = ctypes.c_void_p(0x1000)            # never dereferenced: the call fails first
+    L.lddmm_last_error.restype = ctypes.c_char_p
+    for m in ((1 << 30) + 1, 2 ** 31 - 1, -1):
+        assert L.lddmm_velocity(None, P, fake, fake, m, fake, fake, None) == lddmm.EINVAL
+        assert b"m must be" in L.lddmm_last_error(None)
+        assert L.lddmm_flow(None, P, fake, fake, m, fake, fake, None, None,
+                            None) == lddmm.EINVAL
+        assert b"m must be" in L.lddmm_last_error(None)

@@ -32,6 +32,10 @@ def test_job_footprint_grows_with_n_and_T():
     assert lddmm.job_footprint(cfg64, 8000) > b
     with pytest.raises(lddmm.LddmmError):
         lddmm.job_footprint(cfg, 0)
+    with pytest.raises(lddmm.LddmmError):
+        lddmm.job_footprint(cfg, (1 << 26) + 1)
+    with pytest.raises(lddmm.LddmmError):
+        lddmm.job_footprint(lddmm.server_config((1 << 20) + 1, "fp32c"), 500)
 
 
 def test_auto_checkpoint_choice():
