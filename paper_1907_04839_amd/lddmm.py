@@ -206,6 +206,12 @@ class Context:
     def handle(self):
         return self._h
 
+    def _pts(self, t: torch.Tensor, name: str, n: int) -> int:
+        ptr = _pts(t, name, n)
+        if t.device.index != self.device:
+            raise ValueError(f"{name} is on cuda:{t.device.index}, the context on cuda:{self.device}")
+        return ptr
+
     def close(self):
         if getattr(self, "_h", None):
             lib().lddmm_ctx_destroy(self._h)
@@ -232,8 +238,8 @@ class Context:
         q1 = torch.empty_like(q0)
         p1 = torch.empty_like(q0)
         H0 = torch.empty((), dtype=torch.float64, device=q0.device)
-        _check(lib().lddmm_shoot_forward(self._h, ctypes.byref(prm), _pts(q0, "q0", n),
-                                         _pts(p0, "p0", n), q1.data_ptr(), p1.data_ptr(),
+        _check(lib().lddmm_shoot_forward(self._h, ctypes.byref(prm), self._pts(q0, "q0", n),
+                                         self._pts(p0, "p0", n), q1.data_ptr(), p1.data_ptr(),
                                          H0.data_ptr(), _stream(stream)), self._h)
         return q1, p1, H0
 
@@ -244,8 +250,8 @@ class Context:
         n, m = q.shape[0], x.shape[0]
         prm = make_params(n, 1, sigma, 0.0, precision, dim=dim)
         v = torch.empty_like(x) if out is None else out
-        _check(lib().lddmm_velocity(self._h, ctypes.byref(prm), _pts(q, "q", n), _pts(p, "p", n),
-                                    m, _pts(x, "x", m), _pts(v, "v", m), _stream(stream)),
+        _check(lib().lddmm_velocity(self._h, ctypes.byref(prm), self._pts(q, "q", n), self._pts(p, "p", n),
+                                    m, self._pts(x, "x", m), self._pts(v, "v", m), _stream(stream)),
                self._h)
         return v
 
@@ -261,8 +267,8 @@ class Context:
         x1 = torch.empty_like(x0) if out is None else out
         q1 = torch.empty_like(q0) if want_landmarks else None
         p1 = torch.empty_like(q0) if want_landmarks else None
-        _check(lib().lddmm_flow(self._h, ctypes.byref(prm), _pts(q0, "q0", n), _pts(p0, "p0", n),
-                                m, _pts(x0, "x0", m), _pts(x1, "x1", m),
+        _check(lib().lddmm_flow(self._h, ctypes.byref(prm), self._pts(q0, "q0", n), self._pts(p0, "p0", n),
+                                m, self._pts(x0, "x0", m), self._pts(x1, "x1", m),
                                 q1.data_ptr() if q1 is not None else None,
                                 p1.data_ptr() if p1 is not None else None, _stream(stream)),
                self._h)
@@ -294,15 +300,15 @@ class Context:
             gq = torch.empty_like(q0) if want_grad_q0 else None
             gx = torch.empty_like(q0) if want_grad_x else None
             _check(lib().lddmm_shoot_grad_all(
-                self._h, ctypes.byref(prm), _pts(q0, "q0", n), _pts(p0, "p0", n),
-                _pts(target, "target", n), out3.data_ptr(), _pts(grad, "grad", n),
+                self._h, ctypes.byref(prm), self._pts(q0, "q0", n), self._pts(p0, "p0", n),
+                self._pts(target, "target", n), out3.data_ptr(), self._pts(grad, "grad", n),
                 gq.data_ptr() if gq is not None else None,
                 gx.data_ptr() if gx is not None else None,
                 q1.data_ptr() if q1 is not None else None, _stream(stream)), self._h)
             return GradResult(out3[0], out3[1], out3[2], grad, q1, gq, gx)
-        _check(lib().lddmm_shoot_grad(self._h, ctypes.byref(prm), _pts(q0, "q0", n),
-                                      _pts(p0, "p0", n), _pts(target, "target", n),
-                                      out3.data_ptr(), _pts(grad, "grad", n),
+        _check(lib().lddmm_shoot_grad(self._h, ctypes.byref(prm), self._pts(q0, "q0", n),
+                                      self._pts(p0, "p0", n), self._pts(target, "target", n),
+                                      out3.data_ptr(), self._pts(grad, "grad", n),
                                       q1.data_ptr() if q1 is not None else None,
                                       _stream(stream)), self._h)
         return GradResult(out3[0], out3[1], out3[2], grad, q1)
@@ -323,8 +329,8 @@ class Context:
         out = torch.empty_like(q0) if p0 is None else p0.detach().clone().contiguous()
         res = SolveResult()
         tr = np.full(2 * (o.max_iter + 1), np.nan) if want_trace else None
-        rc = lib().lddmm_solve(self._h, ctypes.byref(prm), ctypes.byref(o), _pts(q0, "q0", n),
-                               _pts(target, "target", n), _pts(out, "p0", n), ctypes.byref(res),
+        rc = lib().lddmm_solve(self._h, ctypes.byref(prm), ctypes.byref(o), self._pts(q0, "q0", n),
+                               self._pts(target, "target", n), self._pts(out, "p0", n), ctypes.byref(res),
                                tr.ctypes.data if tr is not None else None, _stream(stream))
         _check(rc, self._h, allow=(OK, ENOTCONV))
         r = {k: getattr(res, k) for k, _ in SolveResult._fields_}
