@@ -56,19 +56,19 @@ def lib():
         L.oracle_hamiltonian.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, ctypes.c_int]
         L.oracle_hamiltonian.restype = ctypes.c_double
         L.oracle_shoot_forward.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
-                                           _dp, _dp, _dp, _dp, ctypes.c_int]
+                                           _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int]
         L.oracle_shoot_forward.restype = ctypes.c_int
         L.oracle_velocity.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp, _dp,
                                       _dp, ctypes.c_int]
         L.oracle_flow.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp,
-                                  ctypes.c_int, _dp, _dp, _dp, ctypes.c_int]
+                                  ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int]
         L.oracle_flow.restype = ctypes.c_int
         L.oracle_shoot_grad.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                         _dp, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int]
         L.oracle_shoot_grad.restype = ctypes.c_int
         L.oracle_shoot_grad_all.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                             ctypes.c_double, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
-                                            _dp, _dp, ctypes.c_int, ctypes.c_int]
+                                            _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.oracle_shoot_grad_all.restype = ctypes.c_int
         L.oracle_solve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                    _dp, _dp, _dp, ctypes.POINTER(_Opts), ctypes.POINTER(_Result),
@@ -144,8 +144,19 @@ def hamiltonian(q, p, sigma: float, compensated: bool = False) -> float:
     return float(lib().oracle_hamiltonian(q.shape[0], float(sigma), _p(q), _p(p), int(compensated)))
 
 
-def shoot_forward(q0, p0, sigma: float, T: int, traj: bool = False, compensated: bool = False):
-    """Explicit-Euler Hamiltonian flow over [0,1] (Alg. 1, forward loop).
+INTEGRATORS = {"euler": 0, "rk4": 1}
+
+
+def _integrator(name: str) -> int:
+    if name not in INTEGRATORS:
+        raise ValueError("integrator must be 'euler' or 'rk4'")
+    return INTEGRATORS[name]
+
+
+def shoot_forward(q0, p0, sigma: float, T: int, traj: bool = False, compensated: bool = False,
+                  integrator: str = "euler"):
+    """Hamiltonian flow over [0,1] in T explicit Euler steps (Alg. 1, forward
+    loop) or, with integrator="rk4", T classical Runge-Kutta steps.
 
     Returns dict(q1, p1, H0, Hp0[, traj (T+1, 2, N, 3)]).
     """
@@ -155,7 +166,8 @@ def shoot_forward(q0, p0, sigma: float, T: int, traj: bool = False, compensated:
     H0 = ctypes.c_double(0.0)
     tr = np.empty((T + 1, 2, n, 3)) if traj else None
     rc = lib().oracle_shoot_forward(n, int(T), float(sigma), _p(q0), _p(p0), _p(q1), _p(p1),
-                                    ctypes.byref(H0), _p(tr), _p(Hp0), int(compensated))
+                                    ctypes.byref(H0), _p(tr), _p(Hp0), int(compensated),
+                                    _integrator(integrator))
     if rc != 0:
         raise MemoryError("oracle_shoot_forward")
     out = dict(q1=q1, p1=p1, H0=H0.value, Hp0=Hp0)
@@ -173,25 +185,27 @@ def velocity(q, p, x, sigma: float, compensated: bool = False):
     return v
 
 
-def flow(q0, p0, x0, sigma: float, T: int, compensated: bool = False):
+def flow(q0, p0, x0, sigma: float, T: int, compensated: bool = False, integrator: str = "euler"):
     """Points x0 [M,3] carried by the landmark motion from (q0, p0) over T explicit
-    Euler steps of eq. 4's velocity.  Returns dict(x1, q1)."""
+    Euler steps of eq. 4's velocity (integrator="rk4": Runge-Kutta steps of the
+    joint system).  Returns dict(x1, q1)."""
     q0, p0, x0 = _in(q0), _in(p0), _in(x0)
     x1, q1 = np.empty_like(x0), np.empty_like(q0)
     rc = lib().oracle_flow(q0.shape[0], int(T), float(sigma), _p(q0), _p(p0), x0.shape[0], _p(x0),
-                           _p(x1), _p(q1), int(compensated))
+                           _p(x1), _p(q1), int(compensated), _integrator(integrator))
     if rc != 0:
         raise MemoryError("oracle_flow")
     return dict(x1=x1, q1=q1)
 
 
 def shoot_grad(q0, p0, x, sigma: float, lam: float, T: int, compensated: bool = False,
-               all_grads: bool = False, energy: str = "initial"):
+               all_grads: bool = False, energy: str = "initial", integrator: str = "euler"):
     """Loss L = H(q0,p0) + lam |q(1)-x|^2 (eq. 3) and dL/dp0 (exact discrete adjoint).
 
     energy="final" uses H(q(1),p(1)) as the energy term (the loss as Alg. 1
-    evaluates it after the forward loop).  Returns dict(loss, grad, q1, H0
-    (the energy term), mismatch[, grad_q0, grad_x]).
+    evaluates it after the forward loop).  integrator="rk4" takes classical
+    Runge-Kutta steps and the exact adjoint of their stages.  Returns
+    dict(loss, grad, q1, H0 (the energy term), mismatch[, grad_q0, grad_x]).
     """
     if energy not in ("initial", "final"):
         raise ValueError("energy must be 'initial' or 'final'")
@@ -204,7 +218,8 @@ def shoot_grad(q0, p0, x, sigma: float, lam: float, T: int, compensated: bool = 
     terms = np.zeros(2)
     rc = lib().oracle_shoot_grad_all(n, int(T), float(sigma), float(lam), _p(q0), _p(p0), _p(x),
                                      ctypes.byref(loss), _p(grad), _p(gq), _p(gx), _p(q1),
-                                     _p(terms), int(compensated), int(energy == "final"))
+                                     _p(terms), int(compensated), int(energy == "final"),
+                                     _integrator(integrator))
     if rc != 0:
         raise MemoryError("oracle_shoot_grad")
     out = dict(loss=loss.value, grad=grad, q1=q1, H0=float(terms[0]), mismatch=float(terms[1]))

@@ -14,11 +14,17 @@
  *                 Hp_i = dH/dp_i = sum_j g_ij p_j
  *                 Hq_i = dH/dq_i = -c sum_j g_ij (p_i.p_j)(q_i - q_j),  c = 1/sigma^2
  *   integrator  explicit Euler, dt = 1/T, q and p updated simultaneously
- *               from the step-t values (Alg. 1, forward loop)
+ *               from the step-t values (Alg. 1, forward loop); optionally
+ *               (an extension: the paper takes Euler steps) the classical
+ *               fourth-order Runge-Kutta step of the same field f = (Hp, -Hq):
+ *                 k1 = f(y), k2 = f(y + h/2 k1), k3 = f(y + h/2 k2),
+ *                 k4 = f(y + h k3),  y' = y + h/6 (k1 + 2 k2 + 2 k3 + k4)
  *   objective   L(p0) = H(q0,p0) + lambda sum_i |q_i(1) - x_i|^2   (eq. 3)
  *   gradient    exact adjoint of the discrete Euler map, run backwards in
  *               time (Alg. 1, backward loop); dL/dp0 = b(0) + Hp(q0,p0),
- *               and also dL/dq0 = a(0) + Hq(q0,p0), dL/dx = -2 lambda (q(1)-x)
+ *               and also dL/dq0 = a(0) + Hq(q0,p0), dL/dx = -2 lambda (q(1)-x).
+ *               For the Runge-Kutta step, the exact adjoint of its four
+ *               stage equations (reverse-mode differentiation, see below)
  *   optimiser   L-BFGS on p0 (Sec. 2.1 and Alg. 1, steps (e)-(f)), own
  *               implementation: two-loop recursion + strong-Wolfe search
  *   velocity    v(x,t) = sum_l g(|q_l(t) - x|) p_l(t) at any point x (eq. 4),
@@ -40,7 +46,17 @@
  *     B_i =   sum_j g_ij [ a_j + c e_ij p_j ]
  * (A = H_qp a - H_qq b and B = H_pp a - H_pq b, the Hessian blocks of H).
  * This is derived, not printed: the paper names StepBackward but gives no
- * formula for it.
+ * formula for it.  (A, B) = J(y)^T (a, b), J the Jacobian of f at y = (q, p).
+ *
+ * The Runge-Kutta adjoint.  With stage states Y1 = y, Y2 = y + h/2 k1,
+ * Y3 = y + h/2 k2, Y4 = y + h k3 and lambda' = dL/dy', differentiating the
+ * stage equations in reverse gives
+ *     w4 = J(Y4)^T (h/6 lambda')
+ *     w3 = J(Y3)^T (h/3 lambda' + h w4)
+ *     w2 = J(Y2)^T (h/3 lambda' + h/2 w3)
+ *     w1 = J(Y1)^T (h/6 lambda' + h/2 w2)
+ *     lambda = dL/dy = lambda' + w1 + w2 + w3 + w4.
+ * The oracle recomputes the stage states from the stored state of the step.
  *
  * Every sum over j runs in index order 0..N-1 including j = i; rows are
  * split over threads, which does not change any row's order of summation,
@@ -251,15 +267,59 @@ void oracle_pair_adjoint_rows(int n, double sigma, const double *q, const double
 /* forward shooting (Alg. 1, forward loop)                                  */
 /* ------------------------------------------------------------------------ */
 
+/* The four stages of one Runge-Kutta step from (q, p): stage states
+ * Ys[s] = [q (3N), p (3N)] and their fields (Hq, Hp) in Hqs[s], Hps[s]
+ * (k_s = (Hp, -Hq) at Ys[s]).  Buffers are 3N (states 6N) each. */
+static void rk4_stages(int n, double sigma, double h, const double *q, const double *p,
+                       double *Ys[4], double *Hqs[4], double *Hps[4], int compensated) {
+    size_t m = 3 * (size_t)n;
+    const double c[4] = {0.0, 0.5 * h, 0.5 * h, h};   /* Y_s = y + c_s k_{s-1} */
+    for (int st = 0; st < 4; ++st) {
+        double *Yq = Ys[st], *Yp = Ys[st] + m;
+        for (size_t k = 0; k < m; ++k) {
+            if (st == 0) { Yq[k] = q[k]; Yp[k] = p[k]; }
+            else {
+                Yq[k] = q[k] + c[st] * Hps[st - 1][k];
+                Yp[k] = p[k] - c[st] * Hqs[st - 1][k];
+            }
+        }
+        oracle_pair_forward(n, sigma, Yq, Yp, Hqs[st], Hps[st], compensated);
+    }
+}
+
+/* Scratch of 4 stage states and 4 fields for the Runge-Kutta step. */
+typedef struct { double *Y[4], *Hq[4], *Hp[4]; } rk4_buf;
+
+static int rk4_alloc(rk4_buf *b, int n) {
+    size_t m = 3 * (size_t)n;
+    int ok = 1;
+    for (int st = 0; st < 4; ++st) {
+        b->Y[st] = (double *)malloc(sizeof(double) * 2 * m);
+        b->Hq[st] = (double *)malloc(sizeof(double) * m);
+        b->Hp[st] = (double *)malloc(sizeof(double) * m);
+        ok = ok && b->Y[st] && b->Hq[st] && b->Hp[st];
+    }
+    return ok;
+}
+
+static void rk4_free(rk4_buf *b) {
+    for (int st = 0; st < 4; ++st) { free(b->Y[st]); free(b->Hq[st]); free(b->Hp[st]); }
+}
+
 /* traj (optional): (T+1) slots of [q (3N), p (3N)]; slot t = state at step t.
  * Hp0 (optional): Hp(q0,p0), 3N.  Returns 0, or -2 when memory runs out. */
 static int shoot_forward_impl(int n, int T, double sigma, const double *q0, const double *p0,
                               double *q1, double *p1, double *H0, double *traj, double *Hp0,
-                              double *Hq0, int compensated) {
+                              double *Hq0, int compensated, int rk4) {
     size_t m = 3 * (size_t)n;
     double *q = (double *)malloc(sizeof(double) * m), *p = (double *)malloc(sizeof(double) * m);
     double *Hq = (double *)malloc(sizeof(double) * m), *Hp = (double *)malloc(sizeof(double) * m);
-    if (!q || !p || !Hq || !Hp) { free(q); free(p); free(Hq); free(Hp); return -2; }
+    rk4_buf rb;
+    memset(&rb, 0, sizeof rb);
+    if (!q || !p || !Hq || !Hp || (rk4 && !rk4_alloc(&rb, n))) {
+        free(q); free(p); free(Hq); free(Hp); rk4_free(&rb);
+        return -2;
+    }
     memcpy(q, q0, sizeof(double) * m);
     memcpy(p, p0, sizeof(double) * m);
     const double dt = 1.0 / T;
@@ -268,7 +328,13 @@ static int shoot_forward_impl(int n, int T, double sigma, const double *q0, cons
             memcpy(traj + (size_t)t * 2 * m, q, sizeof(double) * m);
             memcpy(traj + (size_t)t * 2 * m + m, p, sizeof(double) * m);
         }
-        oracle_pair_forward(n, sigma, q, p, Hq, Hp, compensated);
+        if (rk4) {
+            rk4_stages(n, sigma, dt, q, p, rb.Y, rb.Hq, rb.Hp, compensated);
+            memcpy(Hq, rb.Hq[0], sizeof(double) * m);   /* the field at the step's state */
+            memcpy(Hp, rb.Hp[0], sizeof(double) * m);
+        } else {
+            oracle_pair_forward(n, sigma, q, p, Hq, Hp, compensated);
+        }
         if (t == 0) {
             if (Hp0) memcpy(Hp0, Hp, sizeof(double) * m);
             if (Hq0) memcpy(Hq0, Hq, sizeof(double) * m);
@@ -278,11 +344,21 @@ static int shoot_forward_impl(int n, int T, double sigma, const double *q0, cons
                 *H0 = 0.5 * acc_get(&h);
             }
         }
-        for (size_t k = 0; k < m; ++k) {   /* simultaneous Euler update */
-            q[k] = q[k] + dt * Hp[k];
-            p[k] = p[k] - dt * Hq[k];
+        if (rk4) {
+            for (size_t k = 0; k < m; ++k) {   /* y' = y + h/6 (k1 + 2 k2 + 2 k3 + k4) */
+                q[k] = q[k] + dt / 6.0 * (rb.Hp[0][k] + 2.0 * rb.Hp[1][k] + 2.0 * rb.Hp[2][k]
+                                          + rb.Hp[3][k]);
+                p[k] = p[k] - dt / 6.0 * (rb.Hq[0][k] + 2.0 * rb.Hq[1][k] + 2.0 * rb.Hq[2][k]
+                                          + rb.Hq[3][k]);
+            }
+        } else {
+            for (size_t k = 0; k < m; ++k) {   /* simultaneous Euler update */
+                q[k] = q[k] + dt * Hp[k];
+                p[k] = p[k] - dt * Hq[k];
+            }
         }
     }
+    rk4_free(&rb);
     if (traj) {
         memcpy(traj + (size_t)T * 2 * m, q, sizeof(double) * m);
         memcpy(traj + (size_t)T * 2 * m + m, p, sizeof(double) * m);
@@ -293,10 +369,12 @@ static int shoot_forward_impl(int n, int T, double sigma, const double *q0, cons
     return 0;
 }
 
+/* integrator: 0 explicit Euler, 1 classical Runge-Kutta (fourth order) */
 int oracle_shoot_forward(int n, int T, double sigma, const double *q0, const double *p0,
                          double *q1, double *p1, double *H0, double *traj, double *Hp0,
-                         int compensated) {
-    return shoot_forward_impl(n, T, sigma, q0, p0, q1, p1, H0, traj, Hp0, NULL, compensated);
+                         int compensated, int integrator) {
+    return shoot_forward_impl(n, T, sigma, q0, p0, q1, p1, H0, traj, Hp0, NULL, compensated,
+                              integrator == 1);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -334,9 +412,54 @@ void oracle_velocity(int n, int m, double sigma, const double *q, const double *
 /* Flow of m points x0 [m,3] along the landmark motion from (q0, p0): at each
  * of the T steps the points take the velocity of the landmark state at step
  * t, and landmarks and points are then updated together.  x1 [m,3] receives
- * the points at t = 1; q1 (optional) the landmarks.  Returns 0 or -2. */
+ * the points at t = 1; q1 (optional) the landmarks.  Returns 0 or -2.
+ * integrator 1: the Runge-Kutta step of the joint system (landmarks and
+ * points), each point stage taking the velocity of the landmark stage state. */
 int oracle_flow(int n, int T, double sigma, const double *q0, const double *p0, int m,
-                const double *x0, double *x1, double *q1, int compensated) {
+                const double *x0, double *x1, double *q1, int compensated, int integrator) {
+    if (integrator == 1) {
+        size_t nn = 3 * (size_t)n, mm = 3 * (size_t)m;
+        double *q = (double *)malloc(sizeof(double) * nn), *p = (double *)malloc(sizeof(double) * nn);
+        double *x = (double *)malloc(sizeof(double) * (mm ? mm : 1));
+        double *X = (double *)malloc(sizeof(double) * (mm ? mm : 1));
+        double *v[4];
+        rk4_buf rb;
+        memset(&rb, 0, sizeof rb);
+        int ok = q && p && x && X && rk4_alloc(&rb, n);
+        for (int st = 0; st < 4; ++st) {
+            v[st] = (double *)malloc(sizeof(double) * (mm ? mm : 1));
+            ok = ok && v[st];
+        }
+        if (!ok) {
+            free(q); free(p); free(x); free(X); rk4_free(&rb);
+            for (int st = 0; st < 4; ++st) free(v[st]);
+            return -2;
+        }
+        memcpy(q, q0, sizeof(double) * nn);
+        memcpy(p, p0, sizeof(double) * nn);
+        if (mm) memcpy(x, x0, sizeof(double) * mm);
+        const double h = 1.0 / T, c[4] = {0.0, 0.5 / T, 0.5 / T, 1.0 / T};
+        for (int t = 0; t < T; ++t) {
+            rk4_stages(n, sigma, h, q, p, rb.Y, rb.Hq, rb.Hp, compensated);
+            for (int st = 0; st < 4; ++st) {   /* X_s = x + c_s v_{s-1} */
+                for (size_t k = 0; k < mm; ++k) X[k] = st == 0 ? x[k] : x[k] + c[st] * v[st - 1][k];
+                oracle_velocity(n, m, sigma, rb.Y[st], rb.Y[st] + nn, X, v[st], compensated);
+            }
+            for (size_t k = 0; k < nn; ++k) {
+                q[k] = q[k] + h / 6.0 * (rb.Hp[0][k] + 2.0 * rb.Hp[1][k] + 2.0 * rb.Hp[2][k]
+                                         + rb.Hp[3][k]);
+                p[k] = p[k] - h / 6.0 * (rb.Hq[0][k] + 2.0 * rb.Hq[1][k] + 2.0 * rb.Hq[2][k]
+                                         + rb.Hq[3][k]);
+            }
+            for (size_t k = 0; k < mm; ++k)
+                x[k] = x[k] + h / 6.0 * (v[0][k] + 2.0 * v[1][k] + 2.0 * v[2][k] + v[3][k]);
+        }
+        if (mm) memcpy(x1, x, sizeof(double) * mm);
+        if (q1) memcpy(q1, q, sizeof(double) * nn);
+        free(q); free(p); free(x); free(X); rk4_free(&rb);
+        for (int st = 0; st < 4; ++st) free(v[st]);
+        return 0;
+    }
     size_t nn = 3 * (size_t)n, mm = 3 * (size_t)m;
     double *q = (double *)malloc(sizeof(double) * nn), *p = (double *)malloc(sizeof(double) * nn);
     double *Hq = (double *)malloc(sizeof(double) * nn), *Hp = (double *)malloc(sizeof(double) * nn);
@@ -382,20 +505,26 @@ int oracle_flow(int n, int T, double sigma, const double *q0, const double *p0, 
 int oracle_shoot_grad_all(int n, int T, double sigma, double lambda, const double *q0,
                           const double *p0, const double *x, double *loss, double *grad,
                           double *grad_q0, double *grad_x, double *q1, double *terms,
-                          int compensated, int energy_final) {
+                          int compensated, int energy_final, int integrator) {
+    const int rk4 = integrator == 1;
     size_t m = 3 * (size_t)n;
     double *traj = (double *)malloc(sizeof(double) * (size_t)(T + 1) * 2 * m);
     double *Hp0 = (double *)malloc(sizeof(double) * m), *Hq0 = (double *)malloc(sizeof(double) * m);
     double *a = (double *)malloc(sizeof(double) * m), *b = (double *)malloc(sizeof(double) * m);
     double *A = (double *)malloc(sizeof(double) * m), *B = (double *)malloc(sizeof(double) * m);
     double *HqT = (double *)malloc(sizeof(double) * m), *HpT = (double *)malloc(sizeof(double) * m);
-    if (!traj || !Hp0 || !Hq0 || !a || !b || !A || !B || !HqT || !HpT) {
+    double *ua = (double *)malloc(sizeof(double) * m), *ub = (double *)malloc(sizeof(double) * m);
+    double *la = (double *)malloc(sizeof(double) * m), *lb = (double *)malloc(sizeof(double) * m);
+    rk4_buf rb;
+    memset(&rb, 0, sizeof rb);
+    if (!traj || !Hp0 || !Hq0 || !a || !b || !A || !B || !HqT || !HpT || !ua || !ub || !la ||
+        !lb || (rk4 && !rk4_alloc(&rb, n))) {
         free(traj); free(Hp0); free(Hq0); free(a); free(b); free(A); free(B);
-        free(HqT); free(HpT);
+        free(HqT); free(HpT); free(ua); free(ub); free(la); free(lb); rk4_free(&rb);
         return -2;
     }
     double E = 0.0;
-    shoot_forward_impl(n, T, sigma, q0, p0, NULL, NULL, &E, traj, Hp0, Hq0, compensated);
+    shoot_forward_impl(n, T, sigma, q0, p0, NULL, NULL, &E, traj, Hp0, Hq0, compensated, rk4);
     const double *qT = traj + (size_t)T * 2 * m, *pT = qT + m;
     if (energy_final) {   /* H(q(1),p(1)) = 1/2 sum_i p_i(1) . Hp_i(q(1),p(1)) */
         oracle_pair_forward(n, sigma, qT, pT, HqT, HpT, compensated);
@@ -419,12 +548,34 @@ int oracle_shoot_grad_all(int n, int T, double sigma, double lambda, const doubl
     const double dt = 1.0 / T;
     for (int t = T - 1; t >= 0; --t) {
         const double *qt = traj + (size_t)t * 2 * m, *pt = qt + m;
-        oracle_pair_adjoint(n, sigma, qt, pt, a, b, A, B, compensated);
-        for (size_t k = 0; k < m; ++k) {   /* simultaneous update */
-            a[k] = a[k] + dt * A[k];
-            b[k] = b[k] + dt * B[k];
+        if (!rk4) {
+            oracle_pair_adjoint(n, sigma, qt, pt, a, b, A, B, compensated);
+            for (size_t k = 0; k < m; ++k) {   /* simultaneous update */
+                a[k] = a[k] + dt * A[k];
+                b[k] = b[k] + dt * B[k];
+            }
+            continue;
         }
+        /* Runge-Kutta step: (a, b) = lambda' on entry; stage adjoints from the
+         * last stage to the first, accumulated into (la, lb) */
+        rk4_stages(n, sigma, dt, qt, pt, rb.Y, rb.Hq, rb.Hp, compensated);
+        const double wl[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};   /* weight of lambda' */
+        const double wn[4] = {0.5 * dt, 0.5 * dt, dt, 0.0};             /* of w_{s+1} */
+        memcpy(la, a, sizeof(double) * m);
+        memcpy(lb, b, sizeof(double) * m);
+        for (int st = 3; st >= 0; --st) {
+            for (size_t k = 0; k < m; ++k) {   /* u_s = wl_s lambda' + wn_s w_{s+1} */
+                ua[k] = wl[st] * a[k] + (st < 3 ? wn[st] * A[k] : 0.0);
+                ub[k] = wl[st] * b[k] + (st < 3 ? wn[st] * B[k] : 0.0);
+            }
+            oracle_pair_adjoint(n, sigma, rb.Y[st], rb.Y[st] + m, ua, ub, A, B, compensated);
+            for (size_t k = 0; k < m; ++k) { la[k] += A[k]; lb[k] += B[k]; }   /* w_s */
+        }
+        memcpy(a, la, sizeof(double) * m);
+        memcpy(b, lb, sizeof(double) * m);
     }
+    rk4_free(&rb);
+    free(ua); free(ub); free(la); free(lb);
     if (grad)
         for (size_t k = 0; k < m; ++k) grad[k] = b[k] + (energy_final ? 0.0 : Hp0[k]);
     if (grad_q0)
@@ -437,7 +588,7 @@ int oracle_shoot_grad(int n, int T, double sigma, double lambda, const double *q
                       const double *p0, const double *x, double *loss, double *grad,
                       double *q1, double *terms, int compensated) {
     return oracle_shoot_grad_all(n, T, sigma, lambda, q0, p0, x, loss, grad, NULL, NULL, q1,
-                                 terms, compensated, 0);
+                                 terms, compensated, 0, 0);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -593,3 +593,142 @@ def test_final_and_initial_energy_losses_converge_as_dt_shrinks(orc):
         b = orc.shoot_grad(q0, p0, x, 1.0, 1.0, T, energy="final")
         d.append(abs(a["loss"] - b["loss"]))
     assert d[0] > 0 and 1.8 < d[0] / d[1] < 2.2 and 1.8 < d[1] / d[2] < 2.2
+
+
+# ---------------------------------------------------------------- Runge-Kutta steps
+
+def _dense_field(y, n, sigma):
+    """(dq/dt, dp/dt) = (Hp, -Hq) of eq. 2 with dense matrices, for scipy's solver."""
+    q, p = y[: 3 * n].reshape(n, 3), y[3 * n:].reshape(n, 3)
+    D = q[:, None, :] - q[None, :, :]
+    G = np.exp(-(D ** 2).sum(-1) / (2 * sigma ** 2))
+    Hp = G @ p
+    Hq = -(G * (p @ p.T))[:, :, None] * D
+    return np.concatenate([Hp.ravel(), -(Hq.sum(1) / sigma ** 2).ravel()])
+
+
+def test_rk4_single_landmark_moves_in_a_straight_line(orc):
+    q0 = np.array([[0.3, -1.2, 2.0]])
+    p0 = np.array([[0.7, 0.1, -0.4]])
+    r = orc.shoot_forward(q0, p0, 1.3, 7, integrator="rk4")
+    np.testing.assert_allclose(r["q1"], q0 + p0, rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(r["p1"], p0)
+
+
+def test_rk4_converges_at_fourth_order(orc):
+    """Against scipy's DOP853 solution of Hamilton's equations (dense field):
+    halving dt divides the Runge-Kutta error by ~16 and the Euler error by ~2."""
+    from scipy.integrate import solve_ivp
+    q0, p0, _ = rand(71, 6, spread=1.0, p_scale=0.8)
+    sigma, n = 1.2, 6
+    sol = solve_ivp(lambda t, y: _dense_field(y, n, sigma), (0.0, 1.0),
+                    np.concatenate([q0.ravel(), p0.ravel()]), method="DOP853",
+                    rtol=1e-13, atol=1e-14)
+    exact = sol.y[:, -1]
+    err = {}
+    for integ in ("rk4", "euler"):
+        e = []
+        for T in (4, 8, 16, 32):
+            r = orc.shoot_forward(q0, p0, sigma, T, integrator=integ)
+            e.append(np.abs(np.concatenate([r["q1"].ravel(), r["p1"].ravel()]) - exact).max())
+        err[integ] = e
+    rk = err["rk4"]
+    assert rk[0] < 1e-2
+    assert all(12.0 < rk[k] / rk[k + 1] < 20.0 for k in range(3)), rk
+    eu = err["euler"]
+    assert all(1.6 < eu[k] / eu[k + 1] < 2.4 for k in range(3)), eu
+
+
+@pytest.mark.parametrize("seed,n,T", [(81, 1, 3), (82, 5, 2), (83, 9, 4)])
+def test_rk4_gradient_matches_central_differences(orc, seed, n, T):
+    q0, p0, rng = rand(seed, n, spread=1.2, p_scale=0.7)
+    x = q0 + rng.standard_normal(q0.shape)
+    sigma, lam = 1.3, 1.4
+    r = orc.shoot_grad(q0, p0, x, sigma, lam, T, integrator="rk4", all_grads=True)
+    eps = 1e-6
+    fd = np.zeros_like(p0)
+    for i in range(n):
+        for d in range(3):
+            pp, pm = p0.copy(), p0.copy()
+            pp[i, d] += eps
+            pm[i, d] -= eps
+            fd[i, d] = (orc.shoot_grad(q0, pp, x, sigma, lam, T, integrator="rk4")["loss"]
+                        - orc.shoot_grad(q0, pm, x, sigma, lam, T, integrator="rk4")["loss"]) \
+                / (2 * eps)
+    assert rel(r["grad"], fd) < 2e-8
+
+
+def _torch_loss_rk4(q0, p0, x, sigma, lam, T, final_energy=False):
+    """Dense torch model: Hamilton's equations by autograd, classical
+    Runge-Kutta steps unrolled, the energy at t = 0 (or t = 1)."""
+    import torch
+    h = 1.0 / T
+
+    def ham(q, p):
+        d2 = ((q[:, None, :] - q[None, :, :]) ** 2).sum(-1)
+        return 0.5 * (torch.exp(-d2 / (2 * sigma ** 2)) * (p @ p.T)).sum()
+
+    def f(q, p):
+        gq, gp = torch.autograd.grad(ham(q, p), (q, p), create_graph=True)
+        return gp, -gq
+    q, p = q0, p0
+    for _ in range(T):
+        k1 = f(q, p)
+        k2 = f(q + h / 2 * k1[0], p + h / 2 * k1[1])
+        k3 = f(q + h / 2 * k2[0], p + h / 2 * k2[1])
+        k4 = f(q + h * k3[0], p + h * k3[1])
+        q = q + h / 6 * (k1[0] + 2 * k2[0] + 2 * k3[0] + k4[0])
+        p = p + h / 6 * (k1[1] + 2 * k2[1] + 2 * k3[1] + k4[1])
+    E = ham(q, p) if final_energy else ham(q0, p0)
+    return E + lam * ((q - x) ** 2).sum()
+
+
+@pytest.mark.parametrize("energy", ["initial", "final"])
+def test_rk4_gradients_match_dense_autograd_model(orc, energy):
+    import torch
+    q0, p0, rng = rand(91, 12, spread=1.4, p_scale=0.6)
+    x = q0 + rng.standard_normal(q0.shape)
+    sigma, lam, T = 1.1, 1.7, 4
+    tq = torch.tensor(q0, dtype=torch.float64, requires_grad=True)
+    tp = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    tx = torch.tensor(x, dtype=torch.float64, requires_grad=True)
+    L = _torch_loss_rk4(tq, tp, tx, sigma, lam, T, final_energy=energy == "final")
+    gp, gq, gx = torch.autograd.grad(L, (tp, tq, tx))
+    r = orc.shoot_grad(q0, p0, x, sigma, lam, T, integrator="rk4", all_grads=True, energy=energy)
+    assert abs(r["loss"] - L.item()) < 1e-13 * abs(L.item())
+    assert rel(r["grad"], gp.numpy()) < 1e-12
+    assert rel(r["grad_q0"], gq.numpy()) < 1e-12
+    assert rel(r["grad_x"], gx.numpy()) < 1e-12
+
+
+def test_rk4_flow_of_the_landmarks_is_their_trajectory(orc):
+    q0, p0, _ = rand(93, 11)
+    r = orc.flow(q0, p0, q0, 1.5, 6, integrator="rk4")
+    np.testing.assert_allclose(r["x1"], r["q1"], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(r["q1"], orc.shoot_forward(q0, p0, 1.5, 6, integrator="rk4")["q1"],
+                               rtol=0, atol=1e-14)
+
+
+def test_rk4_single_landmark_flow_converges_at_fourth_order(orc):
+    """The scalar ODE of the single-landmark flow (see the Euler test above),
+    integrated by the joint Runge-Kutta step: the error falls ~16x per halving."""
+    from scipy.integrate import solve_ivp
+    q0 = np.array([[0.2, -0.1, 0.4]])
+    p0 = np.array([[0.9, 0.5, -0.3]])
+    x0 = np.array([[0.7, 0.3, 0.1], [-0.5, 0.8, 0.2]])
+    sigma = 0.8
+    pp = float(p0[0] @ p0[0])
+    exact = []
+    for k in range(2):
+        r0 = q0[0] - x0[k]
+        rr, rp = float(r0 @ r0), float(r0 @ p0[0])
+
+        def rhs(t, u, rr=rr, rp=rp):
+            w = t - u[0]
+            return [math.exp(-(rr + 2.0 * w * rp + w * w * pp) / (2.0 * sigma ** 2))]
+        sol = solve_ivp(rhs, (0.0, 1.0), [0.0], method="DOP853", rtol=1e-13, atol=1e-15)
+        exact.append(x0[k] + sol.y[0, -1] * p0[0])
+    errs = [float(np.abs(orc.flow(q0, p0, x0, sigma, T, integrator="rk4")["x1"]
+                         - np.array(exact)).max()) for T in (4, 8, 16)]
+    assert errs[0] < 1e-3
+    assert 12.0 < errs[0] / errs[1] < 20.0 and 12.0 < errs[1] / errs[2] < 20.0, errs
