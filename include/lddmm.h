@@ -72,6 +72,19 @@ typedef enum {
  * per evaluation.  The server supports INITIAL only. */
 typedef enum { LDDMM_ENERGY_INITIAL = 0, LDDMM_ENERGY_FINAL = 1 } lddmm_energy;
 
+/* Time stepping of eq. 2 over [0, 1] in T steps of dt = 1/T.  EULER: explicit
+ * Euler steps with q and p updated together (Alg. 1, forward loop).  RK4: the
+ * classical fourth-order Runge-Kutta step of the same field f = (Hp, -Hq),
+ *   k1 = f(y), k2 = f(y + dt/2 k1), k3 = f(y + dt/2 k2), k4 = f(y + dt k3),
+ *   y' = y + dt/6 (k1 + 2 k2 + 2 k3 + k4),
+ * an extension beyond the paper's steps: four pair-sum launches per step
+ * forward and four backward, errors O(dt^4) instead of O(dt).  The gradients
+ * are the exact adjoint of the stage equations, and the flow of points takes
+ * the same stages.  The trajectory keeps the four stage states of every step
+ * (4 T + 1 records; 4 s + 1 with checkpoints every s steps).  The server
+ * takes EULER only. */
+typedef enum { LDDMM_EULER = 0, LDDMM_RK4 = 1 } lddmm_integrator;
+
 typedef struct {
   int32_t n;               /* landmarks, 1..2^26 */
   int32_t T;               /* Euler steps, 1..2^20 (dt = 1/T) */
@@ -88,6 +101,7 @@ typedef struct {
                               instructions per pair) and every z output is 0.
                               Inputs with a non-zero z give undefined results.
                               The server solves 3D problems only. */
+  int32_t integrator;      /* lddmm_integrator (0: Euler steps) */
 } lddmm_params;
 
 typedef struct lddmm_ctx lddmm_ctx;

@@ -43,16 +43,18 @@ class ShootConfig:
     traj_budget_bytes: int = 2 << 30    # trajectory memory allowed before checkpointing
     energy: str = "initial"             # energy term H(q0,p0) ("initial") or H(q(1),p(1))
     dim: int = 3                        # 2: planar problem (every z component 0)
+    integrator: str = "euler"           # "euler" (Alg. 1) or "rk4" (classical Runge-Kutta)
 
     def resolve_ckpt(self, n: int) -> int:
         if self.ckpt_every != "auto":
             return int(self.ckpt_every)
         rec = 64 if self.precision == "fp64" else 32
-        if (self.T + 1) * n * rec <= self.traj_budget_bytes:
+        spt = 4 if self.integrator == "rk4" else 1   # records per step
+        if (spt * self.T + 1) * n * rec <= self.traj_budget_bytes:
             return 0
-        # smallest segment length whose ring of s+1 records fits, at least sqrt(T)
+        # segment length whose ring of spt s + 1 records fits, at most sqrt(T)
         s = max(1, int(math.ceil(math.sqrt(self.T))))
-        while s > 1 and (s + 1) * n * rec > self.traj_budget_bytes:
+        while s > 1 and (spt * s + 1) * n * rec > self.traj_budget_bytes:
             s //= 2
         return s
 
@@ -68,7 +70,7 @@ class ShootLoss(torch.autograd.Function):
                            target.detach().contiguous(), cfg.T, cfg.sigma, cfg.lam,
                            precision=cfg.precision, ckpt_every=cfg.resolve_ckpt(n),
                            want_q1=False, want_grad_q0=want_q0, want_grad_x=want_x,
-                           energy=cfg.energy, dim=cfg.dim)
+                           energy=cfg.energy, dim=cfg.dim, integrator=cfg.integrator)
         saved = [r.grad] + ([r.grad_q0] if want_q0 else []) + ([r.grad_x] if want_x else [])
         actx.save_for_backward(*saved)
         actx.layout = (want_q0, want_x)
@@ -85,7 +87,9 @@ class ShootLoss(torch.autograd.Function):
 
 
 def shoot_loss(p0, q0, target, T: int, sigma: float, lam: float, precision: str = "fp32c",
-               ckpt_every: int | str = "auto", energy: str = "initial") -> torch.Tensor:
+               ckpt_every: int | str = "auto", energy: str = "initial",
+               integrator: str = "euler") -> torch.Tensor:
     """Differentiable loss of eq. 3 (with respect to p0, q0 and target)."""
     return ShootLoss.apply(p0, q0, target,
-                           ShootConfig(T, sigma, lam, precision, ckpt_every, energy=energy))
+                           ShootConfig(T, sigma, lam, precision, ckpt_every, energy=energy,
+                                       integrator=integrator))

@@ -142,6 +142,8 @@ lddmm_status check_params(lddmm_ctx* ctx, const lddmm_params* p) {
     return fail(ctx, LDDMM_EINVAL, "unknown energy term %d", p->energy);
   if (p->dim != 0 && p->dim != 2 && p->dim != 3)
     return fail(ctx, LDDMM_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
+  if (p->integrator != LDDMM_EULER && p->integrator != LDDMM_RK4)
+    return fail(ctx, LDDMM_EINVAL, "unknown integrator %d", p->integrator);
   return LDDMM_OK;
 }
 
@@ -151,8 +153,9 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 struct Layout {
   size_t st, ad, hp0, hq0, xc, cen, h0p, out3, traj, arec, ckpt, partial;
   size_t hpT, hqT, hTp, stT, recT;   // energy at t = 1 only (else empty)
+  size_t rk_acc, rk_lam;             // Runge-Kutta steps only (else empty)
   size_t total;
-  int slots;   // trajectory slots
+  int slots;   // trajectory slots (records: 1 per Euler step, 4 per Runge-Kutta step)
   int nseg;    // checkpoint segments (0 = full trajectory)
 };
 
@@ -171,7 +174,8 @@ Layout make_layout(const lddmm_params& p, const Plan& plan) {
   L.out3 = take(4 * 8);
   const int s = p.ckpt_every;
   const bool ck = s > 0 && s < p.T;
-  L.slots = ck ? s + 1 : p.T + 1;
+  const int spt = p.integrator == LDDMM_RK4 ? 4 : 1;   // records per step
+  L.slots = spt * (ck ? s : p.T) + 1;
   L.nseg = ck ? (p.T + s - 1) / s : 0;
   L.traj = take((size_t)L.slots * n * rb);
   L.arec = take(2 * n * rb);
@@ -183,6 +187,8 @@ Layout make_layout(const lddmm_params& p, const Plan& plan) {
   L.hTp = take(fin ? (size_t)plan.nb * 8 : 0);
   L.stT = take(fin ? 6 * n * 8 : 0);
   L.recT = take(fin ? n * rb : 0);
+  L.rk_acc = take(spt == 4 ? 6 * n * 8 : 0);
+  L.rk_lam = take(spt == 4 ? 6 * n * 8 : 0);
   L.total = off;
   return L;
 }
@@ -217,15 +223,18 @@ struct Job {
   Layout L;
   void* ws;
   double *st, *ad, *hp0, *hq0, *xc, *cen, *h0p, *out3, *ckpt;
-  double *hpT, *hqT, *hTp, *stT;
+  double *hpT, *hqT, *hTp, *stT, *rk_acc, *rk_lam;
   void* recT;
   char *traj, *arec;
   void* partial;
   size_t rb;
   int dim;   // 2 (planar) or 3
+  int spt;   // records per step: 1 (Euler) or 4 (Runge-Kutta stage states)
 
-  void* slot(int t) const {
-    const int k = L.nseg > 0 ? t % L.slots : t;
+  // Record of stage s (0-based) of step t; (t, 0) is the state at step t.
+  void* rec(int t, int s = 0) const {
+    const int r = spt * t + s;
+    const int k = L.nseg > 0 ? r % L.slots : r;
     return traj + (size_t)k * p.n * rb;
   }
   void* arec_buf(int k) const { return arec + (size_t)k * p.n * rb; }
@@ -256,58 +265,78 @@ Job make_job(const lddmm_params& p, void* ws) {
   j.hTp = at<double>(ws, j.L.hTp);
   j.stT = at<double>(ws, j.L.stT);
   j.recT = at<void>(ws, j.L.recT);
+  j.rk_acc = at<double>(ws, j.L.rk_acc);
+  j.rk_lam = at<double>(ws, j.L.rk_lam);
+  j.spt = p.integrator == LDDMM_RK4 ? 4 : 1;
   j.rb = rec_bytes(p.precision);
   j.dim = p.dim == 2 ? 2 : 3;
   return j;
 }
 
-// Forward Euler steps t in [t0, t1).  first: capture Hp(q0,p0) and H0 at t == 0.
+// Forward steps t in [t0, t1): one launch per Euler step, four per Runge-Kutta
+// step (its stages).  first: capture Hp(q0,p0) and H0 at t == 0.
 hipError_t run_forward(const Job& j, int t0, int t1, bool first, bool store_ckpt, hipStream_t s,
                        Timer* tm, bool want_hq0 = false) {
   const int mode = j.p.precision;
+  const int stages = j.spt;
   for (int t = t0; t < t1; ++t) {
-    FwdArgs a{};
-    a.n = j.p.n; a.nb = j.plan.nb; a.S = j.plan.S; a.chunk = j.plan.chunk; a.wchunk = j.plan.wchunk;
-    a.dim = j.dim;
-    a.sc = j.sc;
-    a.rec_t = j.slot(t);
-    a.rec_t1 = j.slot(t + 1);
-    a.st = j.st;
-    a.hp0 = (first && t == 0) ? j.hp0 : nullptr;
-    a.hq0 = (first && t == 0 && want_hq0) ? j.hq0 : nullptr;
-    a.h0_part = (first && t == 0) ? j.h0p : nullptr;
-    const int s_every = j.p.ckpt_every;
-    a.ckpt = (store_ckpt && j.L.nseg > 0 && (t + 1) % s_every == 0 && t + 1 < j.p.T)
-                 ? j.ckpt_state((t + 1) / s_every) : nullptr;
-    a.partial = j.partial;
-    hipError_t e = launch_fwd_step(mode, j.plan, a, s, tm->take(0));
-    if (e != hipSuccess) return e;
+    for (int st = 0; st < stages; ++st) {
+      const bool last = st == stages - 1;   // this launch writes the state of step t + 1
+      FwdArgs a{};
+      a.n = j.p.n; a.nb = j.plan.nb; a.S = j.plan.S; a.chunk = j.plan.chunk;
+      a.wchunk = j.plan.wchunk;
+      a.dim = j.dim;
+      a.rk = stages == 4 ? st + 1 : 0;
+      a.rk_acc = j.rk_acc;
+      a.sc = j.sc;
+      a.rec_t = j.rec(t, st);
+      a.rec_t1 = last ? j.rec(t + 1) : j.rec(t, st + 1);
+      a.st = j.st;
+      const bool t0_field = first && t == 0 && st == 0;   // the field at (q0, p0)
+      a.hp0 = t0_field ? j.hp0 : nullptr;
+      a.hq0 = t0_field && want_hq0 ? j.hq0 : nullptr;
+      a.h0_part = t0_field ? j.h0p : nullptr;
+      const int s_every = j.p.ckpt_every;
+      a.ckpt = (last && store_ckpt && j.L.nseg > 0 && (t + 1) % s_every == 0 && t + 1 < j.p.T)
+                   ? j.ckpt_state((t + 1) / s_every) : nullptr;
+      a.partial = j.partial;
+      hipError_t e = launch_fwd_step(mode, j.plan, a, s, tm->take(0));
+      if (e != hipSuccess) return e;
+    }
   }
   return hipSuccess;
 }
 
-// Adjoint steps t = t1-1 down to t0; *cur is the adjoint record buffer in use.
+// Adjoint steps t = t1-1 down to t0 (Runge-Kutta: stages 4 down to 1 each);
+// *cur is the adjoint record buffer in use.
 hipError_t run_adjoint(const Job& j, int t0, int t1, int* cur, double* grad, hipStream_t s,
                        Timer* tm, double* grad_q0 = nullptr) {
   const int mode = j.p.precision;
+  const int stages = j.spt;
   for (int t = t1 - 1; t >= t0; --t) {
-    AdjArgs a{};
-    a.n = j.p.n; a.nb = j.plan.nb; a.S = j.plan.S; a.chunk = j.plan.chunk; a.wchunk = j.plan.wchunk;
-    a.dim = j.dim;
-    a.sc = j.sc;
-    a.rec_t = j.slot(t);
-    a.arec = j.arec_buf(*cur);
-    a.arec_next = j.arec_buf(*cur ^ 1);
-    a.ad = j.ad;
-    const bool fin = j.p.energy == LDDMM_ENERGY_FINAL;   // then dL/dp0 = b(0), dL/dq0 = a(0)
-    a.hp0 = fin ? nullptr : j.hp0;
-    a.grad = t == 0 ? grad : nullptr;
-    a.hq0 = fin ? nullptr : j.hq0;
-    a.grad_q0 = t == 0 ? grad_q0 : nullptr;
-    a.partial = j.partial;
-    hipError_t e = launch_adj_step(mode, j.plan, a, s, tm->take(1));
-    if (e != hipSuccess) return e;
-    *cur ^= 1;
+    for (int st = stages - 1; st >= 0; --st) {
+      AdjArgs a{};
+      a.n = j.p.n; a.nb = j.plan.nb; a.S = j.plan.S; a.chunk = j.plan.chunk;
+      a.wchunk = j.plan.wchunk;
+      a.dim = j.dim;
+      a.rk = stages == 4 ? st + 1 : 0;
+      a.rk_lam = j.rk_lam;
+      a.sc = j.sc;
+      a.rec_t = j.rec(t, st);
+      a.arec = j.arec_buf(*cur);
+      a.arec_next = j.arec_buf(*cur ^ 1);
+      a.ad = j.ad;
+      const bool fin = j.p.energy == LDDMM_ENERGY_FINAL;   // then dL/dp0 = b(0), dL/dq0 = a(0)
+      const bool end = t == 0 && st == 0;                   // the adjoint at t = 0 is complete
+      a.hp0 = fin ? nullptr : j.hp0;
+      a.grad = end ? grad : nullptr;
+      a.hq0 = fin ? nullptr : j.hq0;
+      a.grad_q0 = end ? grad_q0 : nullptr;
+      a.partial = j.partial;
+      hipError_t e = launch_adj_step(mode, j.plan, a, s, tm->take(1));
+      if (e != hipSuccess) return e;
+      *cur ^= 1;
+    }
   }
   return hipSuccess;
 }
@@ -333,7 +362,7 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
   const lddmm_params* params = &j.p;
   const int n = params->n, T = params->T, mode = params->precision;
   HIP_TRY(ctx, launch_centroid(q0, n, j.cen, s), "centroid");
-  HIP_TRY(ctx, launch_stage(mode, n, q0, p0, target, j.cen, j.sc.k, j.st, j.xc, j.slot(0), s),
+  HIP_TRY(ctx, launch_stage(mode, n, q0, p0, target, j.cen, j.sc.k, j.st, j.xc, j.rec(0), s),
           "stage");
   if (j.L.nseg > 0)
     HIP_TRY(ctx, hipMemcpyAsync(j.ckpt_state(0), j.st, 6 * (size_t)n * 8, hipMemcpyDeviceToDevice, s),
@@ -351,7 +380,7 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
     a.n = n; a.nb = j.plan.nb; a.S = j.plan.S; a.chunk = j.plan.chunk; a.wchunk = j.plan.wchunk;
     a.dim = j.dim;
     a.sc = j.sc;
-    a.rec_t = j.slot(T);
+    a.rec_t = j.rec(T);
     a.rec_t1 = j.recT;
     a.st = j.stT;
     a.hp0 = j.hpT;
@@ -360,9 +389,10 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
     a.partial = j.partial;
     HIP_TRY(ctx, launch_fwd_step(mode, j.plan, a, s, ctx->timer.take(0)), "final energy");
   }
-  HIP_TRY(ctx, launch_loss(mode, n, j.plan.nb, params->lambda, j.sc.bscale, j.st, j.xc, j.cen,
-                           fin ? j.hTp : j.h0p, j.ad, j.arec_buf(0), out3, q1, nullptr, ctx->flag,
-                           grad_x, fin ? j.hqT : nullptr, fin ? j.hpT : nullptr, s),
+  const double rscale = j.spt == 4 ? j.sc.dt / 6.0 : 1.0;   // first stage adjoint: dt/6 lambda
+  HIP_TRY(ctx, launch_loss(mode, n, j.plan.nb, params->lambda, j.sc.bscale, rscale, j.st, j.xc,
+                           j.cen, fin ? j.hTp : j.h0p, j.ad, j.arec_buf(0), out3, q1, nullptr,
+                           ctx->flag, grad_x, fin ? j.hqT : nullptr, fin ? j.hpT : nullptr, s),
           "loss");
   int cur = 0;
   if (j.L.nseg == 0) {
@@ -372,7 +402,7 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
     for (int seg = j.L.nseg - 1; seg >= 0; --seg) {
       const int t0 = seg * every, t1 = std::min(T, t0 + every);
       if (seg != j.L.nseg - 1) {   // the last segment is still in the ring of slots
-        HIP_TRY(ctx, launch_restore(mode, n, j.ckpt_state(seg), j.sc.k, j.st, j.slot(t0), s),
+        HIP_TRY(ctx, launch_restore(mode, n, j.ckpt_state(seg), j.sc.k, j.st, j.rec(t0), s),
                 "restore");
         HIP_TRY(ctx, run_forward(j, t0, t1, false, false, s, &ctx->timer), "recompute step");
       }
@@ -463,7 +493,7 @@ lddmm_status lddmm_shoot_forward(lddmm_ctx* ctx, const lddmm_params* params, con
   const int n = params->n;
   HIP_TRY(ctx, launch_centroid(q0, n, j.cen, s), "centroid");
   HIP_TRY(ctx, launch_stage(params->precision, n, q0, p0, nullptr, j.cen, j.sc.k, j.st, j.xc,
-                            j.slot(0), s), "stage");
+                            j.rec(0), s), "stage");
   HIP_TRY(ctx, run_forward(j, 0, params->T, true, false, s, &ctx->timer), "forward step");
   HIP_TRY(ctx, launch_forward_out(n, j.plan.nb, j.st, j.cen, j.h0p, H0, q1, p1, s), "forward out");
   return LDDMM_OK;
@@ -500,6 +530,7 @@ FlowArgs flow_args(const Job& j, int m, int W) {
   a.n = j.p.n;
   a.m = m;
   a.slots = j.L.slots;
+  a.spt = j.spt;
   a.wchunk = (j.p.n + W - 1) / W;
   a.dim = j.dim;
   a.k = j.sc.k;
@@ -522,6 +553,7 @@ lddmm_status lddmm_velocity(lddmm_ctx* ctx, const lddmm_params* params, const do
   lddmm_params one = *params;   // one state: no trajectory beyond slot 0
   one.T = 1;
   one.ckpt_every = 0;
+  one.integrator = LDDMM_EULER;   // no steps are taken
   Job j;
   lddmm_status st = begin(ctx, &one, &j);
   if (st != LDDMM_OK) return st;
@@ -529,7 +561,7 @@ lddmm_status lddmm_velocity(lddmm_ctx* ctx, const lddmm_params* params, const do
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int n = one.n;
   HIP_TRY(ctx, launch_centroid(q, n, j.cen, s), "centroid");
-  HIP_TRY(ctx, launch_stage(one.precision, n, q, p, nullptr, j.cen, j.sc.k, j.st, j.xc, j.slot(0), s),
+  HIP_TRY(ctx, launch_stage(one.precision, n, q, p, nullptr, j.cen, j.sc.k, j.st, j.xc, j.rec(0), s),
           "stage");
   const int W = flow_waves(n);
   FlowArgs a = flow_args(j, m, W);
@@ -557,7 +589,7 @@ lddmm_status lddmm_flow(lddmm_ctx* ctx, const lddmm_params* params, const double
   const int n = params->n, T = params->T;
   HIP_TRY(ctx, launch_centroid(q0, n, j.cen, s), "centroid");
   HIP_TRY(ctx, launch_stage(params->precision, n, q0, p0, nullptr, j.cen, j.sc.k, j.st, j.xc,
-                            j.slot(0), s), "stage");
+                            j.rec(0), s), "stage");
   const int W = flow_waves(n);
   double* xs = at<double>(ctx->ws, j.L.total);
   // Segments of the landmark forward pass, each followed by the points' steps

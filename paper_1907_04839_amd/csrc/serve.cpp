@@ -537,6 +537,8 @@ lddmm_status lddmm_server_submit(lddmm_server* s, const lddmm_params* p,
   if (p->energy != LDDMM_ENERGY_INITIAL)
     return sfail(s, LDDMM_EINVAL, "the server takes the energy term at t = 0 only");
   if (p->dim == 2) return sfail(s, LDDMM_EINVAL, "the server solves 3D problems only");
+  if (p->integrator != LDDMM_EULER)
+    return sfail(s, LDDMM_EINVAL, "the server takes Euler steps only");
   if (!(p->sigma > 0.0) || !(p->lambda >= 0.0) || !std::isfinite(p->sigma) ||
       !std::isfinite(p->lambda))
     return sfail(s, LDDMM_EINVAL, "sigma must be > 0 and lambda >= 0");

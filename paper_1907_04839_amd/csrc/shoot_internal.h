@@ -40,10 +40,16 @@ struct Scales {
 
 Scales make_scales(double sigma, int T);
 
-// Arguments of one forward Euler step (pair sums + update).
+// Arguments of one forward Euler step, or of one stage of a classical
+// Runge-Kutta step (pair sums + update).
 struct FwdArgs {
   int n, nb, S, chunk, wchunk;
   int dim;              // 3, or 2 for planar problems (z terms left out)
+  int rk;               // 0: Euler step.  1..4: Runge-Kutta stage rk, whose pair
+                        // sums are taken at the stage state in rec_t; stages
+                        // 1-3 write the next stage state's record to rec_t1,
+                        // stage 4 the new state (st, rec_t1)
+  double* rk_acc;       // [6][n] k1 + 2 k2 + 2 k3, built over stages 1-3
   Scales sc;
   const void* rec_t;    // point records at step t (k q, p)
   void* rec_t1;         // point records at step t+1 (written)
@@ -55,10 +61,17 @@ struct FwdArgs {
   void* partial;        // [S][6][n] partial sums when S > 1
 };
 
-// Arguments of one backward (adjoint) Euler step.
+// Arguments of one backward (adjoint) Euler step, or of one stage of the
+// adjoint of a Runge-Kutta step.
 struct AdjArgs {
   int n, nb, S, chunk, wchunk;
   int dim;              // 3, or 2 for planar problems
+  int rk;               // 0: Euler step.  1..4: stage rk of the Runge-Kutta
+                        // adjoint (taken from 4 down to 1): the pair sums give
+                        // w = J(Y_rk)^T u for the stage state in rec_t and the
+                        // stage adjoint u in arec; ad keeps lambda' (the adjoint
+                        // after the step) until stage 1 writes the new one
+  double* rk_lam;       // [6][n] lambda' + the w of the stages taken so far
   Scales sc;
   const void* rec_t;    // point records at step t (k q, p)
   const void* arec;     // adjoint records (a, b_hat) entering the step
@@ -93,7 +106,9 @@ hipError_t launch_adj_step(int mode, const Plan& p, const AdjArgs& a, hipStream_
 struct FlowArgs {
   int n, m;             // landmarks, points
   int t0, t1;           // steps
-  int slots;            // trajectory slots: step t's records are slot t % slots
+  int slots;            // trajectory slots: record r is slot r % slots
+  int spt;              // records per step: 1 (Euler), 4 (Runge-Kutta stage states;
+                        // record spt t + s is stage s + 1 of step t)
   int wchunk;           // landmarks per wave
   int dim;              // 3, or 2 for planar problems
   double k, dt;
@@ -117,10 +132,13 @@ hipError_t launch_flow(int mode, int W, const FlowArgs& a, hipStream_t s,
 // final state) E is H(q(1), p(1)) and the terminal adjoint gains a += HqT, b = HpT.
 // out3 = {loss, E, mismatch}; q1/p1 (optional) receive the final state, uncentred, [n][3].
 // grad_x (optional): dL/dx = -2 lambda (q(1) - x), [n][3].
-hipError_t launch_loss(int mode, int n, int nb, double lambda, double bscale, const double* st,
-                       const double* xc, const double* cen, const double* h0_part, double* ad,
-                       void* arec0, double* out3, double* q1, double* p1, int* flag,
-                       double* grad_x, const double* hqT, const double* hpT, hipStream_t s);
+// arec0 receives the record of rscale (a, b) for the first adjoint launch
+// (1 for Euler steps, dt / 6 for the last stage of a Runge-Kutta step).
+hipError_t launch_loss(int mode, int n, int nb, double lambda, double bscale, double rscale,
+                       const double* st, const double* xc, const double* cen,
+                       const double* h0_part, double* ad, void* arec0, double* out3, double* q1,
+                       double* p1, int* flag, double* grad_x, const double* hqT,
+                       const double* hpT, hipStream_t s);
 // Forward-only epilogue: writes H0 (device scalar) and the final state.
 hipError_t launch_forward_out(int n, int nb, const double* st, const double* cen,
                               const double* h0_part, double* H0, double* q1, double* p1,

@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("T", ctypes.c_int32), ("sigma", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("ckpt_every", ctypes.c_int32), ("energy", ctypes.c_int32),
-                ("dim", ctypes.c_int32)]
+                ("dim", ctypes.c_int32), ("integrator", ctypes.c_int32)]
 
 
 class Timing(ctypes.Structure):
@@ -142,13 +142,17 @@ def _check(rc: int, ctx=None, allow=(OK,)) -> int:
 
 
 ENERGIES = {"initial": 0, "final": 1}
+INTEGRATORS = {"euler": 0, "rk4": 1}
 
 
 def make_params(n: int, T: int, sigma: float, lam: float, precision="fp32c",
-                ckpt_every: int = 0, energy="initial", dim: int = 3) -> Params:
+                ckpt_every: int = 0, energy="initial", dim: int = 3,
+                integrator="euler") -> Params:
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     en = ENERGIES[energy] if isinstance(energy, str) else int(energy)
-    return Params(int(n), int(T), float(sigma), float(lam), prec, int(ckpt_every), en, int(dim))
+    it = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
+    return Params(int(n), int(T), float(sigma), float(lam), prec, int(ckpt_every), en, int(dim),
+                  it)
 
 
 def solve_opts(precision="fp32c", **overrides) -> SolveOpts:
@@ -231,10 +235,11 @@ class Context:
 
     # -- calls -------------------------------------------------------------
     def shoot_forward(self, q0: torch.Tensor, p0: torch.Tensor, T: int, sigma: float,
-                      precision="fp32c", stream=None, dim: int = 3):
-        """Forward Euler flow (Alg. 1 forward loop).  Returns (q1, p1, H0)."""
+                      precision="fp32c", stream=None, dim: int = 3, integrator="euler"):
+        """Forward flow in T Euler steps (Alg. 1 forward loop) or, with
+        integrator="rk4", T classical Runge-Kutta steps.  Returns (q1, p1, H0)."""
         n = q0.shape[0]
-        prm = make_params(n, T, sigma, 0.0, precision, dim=dim)
+        prm = make_params(n, T, sigma, 0.0, precision, dim=dim, integrator=integrator)
         q1 = torch.empty_like(q0)
         p1 = torch.empty_like(q0)
         H0 = torch.empty((), dtype=torch.float64, device=q0.device)
@@ -257,13 +262,13 @@ class Context:
 
     def flow(self, q0: torch.Tensor, p0: torch.Tensor, x0: torch.Tensor, T: int, sigma: float,
              precision="fp32c", ckpt_every: int = 0, want_landmarks: bool = False, stream=None,
-             out: torch.Tensor | None = None, dim: int = 3):
+             out: torch.Tensor | None = None, dim: int = 3, integrator="euler"):
         """Points x0 [M,3] carried along the landmark motion from (q0, p0) (eq. 4).
 
         Returns x1, or (x1, q1, p1) with ``want_landmarks``.  ``out`` may be x0
         itself (in place)."""
         n, m = q0.shape[0], x0.shape[0]
-        prm = make_params(n, T, sigma, 0.0, precision, ckpt_every, dim=dim)
+        prm = make_params(n, T, sigma, 0.0, precision, ckpt_every, dim=dim, integrator=integrator)
         x1 = torch.empty_like(x0) if out is None else out
         q1 = torch.empty_like(q0) if want_landmarks else None
         p1 = torch.empty_like(q0) if want_landmarks else None
@@ -278,14 +283,14 @@ class Context:
                    sigma: float, lam: float, precision="fp32c", ckpt_every: int = 0,
                    want_q1: bool = True, stream=None, out: dict | None = None,
                    want_grad_q0: bool = False, want_grad_x: bool = False,
-                   energy="initial", dim: int = 3) -> GradResult:
+                   energy="initial", dim: int = 3, integrator="euler") -> GradResult:
         """Loss of eq. 3 and its gradient w.r.t. p0 (Alg. 1 ComputeGradient);
         optionally also w.r.t. q0 and the target (lddmm_shoot_grad_all).
 
         ``out`` may hold preallocated ``grad`` [N,3], ``out3`` [3] and ``q1``.
         """
         n = q0.shape[0]
-        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy, dim)
+        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy, dim, integrator)
         out = out or {}
         grad = out.get("grad")
         if grad is None:
@@ -316,13 +321,14 @@ class Context:
     def solve(self, q0: torch.Tensor, target: torch.Tensor, T: int, sigma: float, lam: float,
               precision="fp32c", p0: torch.Tensor | None = None, ckpt_every: int = 0,
               want_trace: bool = False, stream=None, energy="initial", dim: int = 3,
+              integrator="euler",
               **opts) -> dict:
         """L-BFGS registration on the GPU (Alg. 1).  ``opts`` override the
         library defaults (max_iter, m, max_fev, gtol, ftol_rel, c1, c2, init);
         passing ``p0`` selects init = 2 (start from it)."""
         import numpy as np
         n = q0.shape[0]
-        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy, dim)
+        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy, dim, integrator)
         if p0 is not None:
             opts.setdefault("init", 2)
         o = solve_opts(precision, **opts)

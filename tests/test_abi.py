@@ -58,11 +58,17 @@ def test_workspace_size_validation_on_host(lib):
            lddmm.make_params(10, 10, 1.0, 1.0, precision=7),
            lddmm.make_params(10, 10, 1.0, 1.0, ckpt_every=-2),
            lddmm.make_params(10, 10, 1.0, 1.0, energy=2),
-           lddmm.make_params(10, 10, 1.0, 1.0, dim=1), lddmm.make_params(10, 10, 1.0, 1.0, dim=4)]
+           lddmm.make_params(10, 10, 1.0, 1.0, dim=1), lddmm.make_params(10, 10, 1.0, 1.0, dim=4),
+           lddmm.make_params(10, 10, 1.0, 1.0, integrator=2),
+           lddmm.make_params(10, 10, 1.0, 1.0, integrator=-1)]
     for b in bad:
         with pytest.raises(lddmm.LddmmError) as e:
             lddmm.workspace_size(b)
         assert e.value.status == lddmm.EINVAL
+    # Runge-Kutta steps keep 4 T + 1 records (3 T more) and two FP64 [6][N] buffers
+    eu = lddmm.workspace_size(lddmm.make_params(4096, 40, 8.0, 1.0, "fp32c"))
+    rk = lddmm.workspace_size(lddmm.make_params(4096, 40, 8.0, 1.0, "fp32c", integrator="rk4"))
+    assert abs(rk - eu - (3 * 40 * 4096 * 32 + 2 * 48 * 4096)) < 4096
 
 
 def test_status_strings(lib):
