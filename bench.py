@@ -73,12 +73,13 @@ def momentum(pb):
     return pb.p0
 
 
-def time_steps(ctx, dev, pb, precision, steps, warmup, ckpt_every=0, dim=3):
+def time_steps(ctx, dev, pb, precision, steps, warmup, ckpt_every=0, dim=3, integrator="euler"):
     import torch
     q0, x, p0 = dev["q0"], dev["x"], dev["p0"]
     out = dict(grad=torch.empty_like(q0), out3=torch.empty(3, dtype=torch.float64, device=q0.device))
     run = lambda: ctx.shoot_grad(q0, p0, x, pb.T, pb.sigma, pb.lam, precision=precision,  # noqa: E731
-                                 ckpt_every=ckpt_every, want_q1=False, out=out, dim=dim)
+                                 ckpt_every=ckpt_every, want_q1=False, out=out, dim=dim,
+                                 integrator=integrator)
     for _ in range(warmup):
         run()
     torch.cuda.synchronize()
@@ -109,12 +110,12 @@ def step_event_times(ctx, dev, pb, precision, steps):
     return statistics.median(ms), min(ms)
 
 
-def kernel_times(ctx, dev, pb, precision, steps, ckpt_every=0, dim=3):
+def kernel_times(ctx, dev, pb, precision, steps, ckpt_every=0, dim=3, integrator="euler"):
     """Average pair-kernel durations from HIP events recorded on the launch stream."""
     ctx.timing(reset=True)
     ctx.set_timing(True)
     try:
-        time_steps(ctx, dev, pb, precision, steps, 0, ckpt_every, dim)
+        time_steps(ctx, dev, pb, precision, steps, 0, ckpt_every, dim, integrator)
     finally:
         ctx.set_timing(False)
     t = ctx.timing(reset=True)
@@ -307,6 +308,45 @@ def planar_leg(ctx, precision, steps=10):
     return out
 
 
+def rk4_leg(ctx, precision, steps=10):
+    """Classical Runge-Kutta steps on the ellipsoid workload.  T = 10 RK4 steps
+    take as many pair-sum launches (40 forward, 40 adjoint) and pair terms as the
+    workload's T = 40 Euler steps; both are timed, and both flows' q(1) are
+    compared in FP64 with a fine RK4 reference (T = 160)."""
+    import dataclasses
+    import torch
+    pb = workload("ellipsoid4096")
+    p0 = momentum(pb)
+    dev = {k: torch.from_numpy(v).cuda() for k, v in (("q0", pb.q0), ("x", pb.target), ("p0", p0))}
+    rk = dataclasses.replace(pb, T=10)
+    pairs = 2 * 4 * rk.T * pb.n ** 2
+    d_rk, _ = time_steps(ctx, dev, rk, precision, steps, 2, integrator="rk4")
+    d_eu, _ = time_steps(ctx, dev, pb, precision, steps, 2)
+    kt = kernel_times(ctx, dev, rk, precision, 2, integrator="rk4")
+
+    def q1(T, integ, prec="fp64"):
+        r = ctx.shoot_forward(dev["q0"], dev["p0"], T, pb.sigma, precision=prec, integrator=integ)
+        torch.cuda.synchronize()
+        return r[0].cpu().numpy()
+    import numpy as np
+    ref = q1(160, "rk4")
+    err = lambda a: float(np.linalg.norm(a - ref) / np.linalg.norm(ref))  # noqa: E731
+    out = {"workload": f"{pb.name} with T=10 Runge-Kutta steps (N={pb.n})",
+           "pairs_per_s": round(pairs * steps / d_rk, 1),
+           "ms_per_eval": round(1e3 * d_rk / steps, 3),
+           "euler_T40_ms_per_eval": round(1e3 * d_eu / steps, 3),
+           "q1_rel_err_vs_rk4_T160": {"rk4_T10_fp64": err(q1(10, "rk4")),
+                                      "euler_T40_fp64": err(q1(40, "euler")),
+                                      "rk4_T10_" + precision: err(q1(10, "rk4", precision)),
+                                      "euler_T40_" + precision: err(q1(40, "euler", precision))},
+           "roofline": roofline(pb.n, kt, precision=precision)}
+    e = out["q1_rel_err_vs_rk4_T160"]
+    log(f"[bench] rk4: {out['pairs_per_s']:.4g} pair-interactions/s, {out['ms_per_eval']} ms per "
+        f"evaluation (Euler T=40: {out['euler_T40_ms_per_eval']} ms); q(1) error RK4 T=10 "
+        f"{e['rk4_T10_fp64']:.2e} vs Euler T=40 {e['euler_T40_fp64']:.2e}")
+    return out
+
+
 def paper_scale_solve(ctx, precision):
     """A registration at the scale of the paper's own experiment (1847 landmarks,
     T = 40, up to 400 L-BFGS iterations), on the synthetic ellipsoid recipe: the
@@ -426,6 +466,7 @@ def main():
             extra["flow"] = flow_leg(ctx, args.precision)
             extra["paper_scale_solve"] = paper_scale_solve(ctx, args.precision)
             extra["planar"] = planar_leg(ctx, args.precision)
+            extra["rk4"] = rk4_leg(ctx, args.precision)
 
     if args.serve_jobs > 0 and not args.quick:
         extra["serving"] = serving(args.serve_jobs)
