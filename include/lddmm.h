@@ -17,7 +17,8 @@
  *
  * Options per call (lddmm_params): the precision of the pair sums, trajectory
  * checkpointing, the energy term taken at t = 1 instead of t = 0 (the loss as
- * Alg. 1 evaluates it) and a planar specialisation (Sec. 2.5).
+ * Alg. 1 evaluates it), a planar specialisation (Sec. 2.5) and classical
+ * Runge-Kutta steps in place of the Euler steps (an extension).
  *
  * Conventions shared by every call:
  *   - Point sets (q0, p0, target, q1, p1, grad) are DEVICE pointers to [n][3]
