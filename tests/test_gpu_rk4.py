@@ -164,3 +164,32 @@ def test_server_rejects_rk4():
                                               pb.q0.ctypes.data, pb.target.ctypes.data, None,
                                               ctypes.byref(jid))
         assert st == lddmm.EINVAL
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_rk4_planar_equals_3d_and_oracle(gpu_ctx, orc_mt, mode):
+    """Runge-Kutta stages through the planar instances: on z = 0 data bitwise the
+    3D instances' results (gradients, flow), and the oracle's within the bar."""
+    import torch
+    pb = synth.planar(synth.random_problem(91, 700, T=3))
+    args = (to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), pb.T, pb.sigma, pb.lam)
+    kw = dict(precision=mode, ckpt_every=2, want_grad_q0=True, want_grad_x=True,
+              integrator="rk4")
+    r2 = gpu_ctx.shoot_grad(*args, dim=2, **kw)
+    r3 = gpu_ctx.shoot_grad(*args, dim=3, **kw)
+    x = np.concatenate([3.0 * np.random.default_rng(92).standard_normal((900, 2)),
+                        np.zeros((900, 1))], axis=1)
+    f2 = gpu_ctx.flow(args[0], args[1], to_dev(x), pb.T, pb.sigma, precision=mode, dim=2,
+                      integrator="rk4")
+    f3 = gpu_ctx.flow(args[0], args[1], to_dev(x), pb.T, pb.sigma, precision=mode, dim=3,
+                      integrator="rk4")
+    torch.cuda.synchronize()
+    for k in ("grad", "grad_q0", "grad_x", "q1"):
+        np.testing.assert_array_equal(host(getattr(r2, k)), host(getattr(r3, k)), err_msg=k)
+    np.testing.assert_array_equal(host(f2), host(f3))
+    o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, pb.T, all_grads=True,
+                          integrator="rk4")
+    e = max(rel_err(host(r2.grad), o["grad"]), rel_err(host(r2.grad_q0), o["grad_q0"]),
+            abs(r2.loss.item() - o["loss"]) / abs(o["loss"]))
+    print(f"[rk4 planar {mode}] vs oracle {e:.2e}", flush=True)
+    assert e <= TOL[mode]
