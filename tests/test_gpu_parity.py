@@ -96,6 +96,24 @@ def test_gradient_matches_oracle(gpu_ctx, orc_mt, mode, n, T):
     check_grad(g, o, mode, f"grad n={n} T={T}")
 
 
+# Every (waves per workgroup W, j-chunks S) plan that sizes up to 20000 take, at its
+# smallest N and at a ragged N inside its range (N and the per-wave j range not
+# multiples of 64): (1,1) 1 16 31, (2,1) 32 40 47, (2,2) 48 56 63, (4,1) 64 72 79,
+# (4,2) 80 104 127, (8,1) 128 136 143, (8,2) 144 208 271, (8,3) 272 336 399,
+# (8,4) 400 911 19089, (8,8) 912 9800.
+PLAN_SWEEP = [1, 16, 31, 32, 40, 47, 48, 56, 63, 64, 72, 79, 80, 104, 127, 128, 136, 143, 144,
+              208, 271, 272, 336, 399, 400, 911, 912, 9800, 19089]
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32c"])
+@pytest.mark.parametrize("n", PLAN_SWEEP)
+def test_every_launch_plan_matches_oracle(gpu_ctx, orc_mt, mode, n):
+    pb = synth.random_problem(700 + n, n, T=2)
+    g = run_grad(gpu_ctx, pb, mode)
+    o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, 2)
+    check_grad(g, o, mode, f"plan n={n}")
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_box64_workload(gpu_ctx, orc_mt, mode):
     """The 64-landmark box problem (sigma 10, T 10) at p0 = 0 and at a random p0."""
