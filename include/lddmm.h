@@ -36,6 +36,12 @@
  *   - A context serialises its calls: one context must not be used from two
  *     threads at once, nor on two streams whose work overlaps, because every
  *     call reuses the context's workspace.
+ *   - Evaluations (lddmm_shoot_forward/_grad/_grad_all, lddmm_flow) enqueue
+ *     kernels and device-to-device copies only, so a stream capture records
+ *     them into a hipGraph whose replays repeat them.  The workspace must
+ *     already be large enough when capture starts (one uncaptured call of the
+ *     same shape), and a graph stays valid only until a call on a larger
+ *     problem makes the context grow (reallocate) its workspace.
  */
 #ifndef LDDMM_H
 #define LDDMM_H
