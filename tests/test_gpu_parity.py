@@ -288,6 +288,29 @@ def test_invalid_arguments_are_rejected(gpu_ctx):
                                  None, None) == lddmm.EINVAL
 
 
+def test_workspace_beyond_hbm_is_enomem_and_the_context_recovers(orc):
+    """A problem whose workspace cannot exist (2^26 landmarks, 2^20 steps: ~2 PB of
+    trajectory) fails with ENOMEM before anything is enqueued; the same context
+    then evaluates a small problem correctly."""
+    import ctypes
+    import torch
+    from paper_1907_04839_amd import lddmm
+    L = lddmm.lib()
+    q = to_dev(np.zeros((4, 3)))                 # never read: the call fails first
+    out3 = to_dev(np.zeros(3))
+    with lddmm.Context(0) as ctx:
+        prm = lddmm.make_params(1 << 26, 1 << 20, 1.0, 1.0)
+        rc = L.lddmm_shoot_grad(ctx.handle, ctypes.byref(prm), q.data_ptr(), q.data_ptr(),
+                                q.data_ptr(), out3.data_ptr(), q.data_ptr(), None, None)
+        assert rc == lddmm.ENOMEM
+        assert b"hipMalloc" in L.lddmm_last_error(ctx.handle)
+        pb = synth.random_problem(1320, 200, T=4)
+        g = run_grad(ctx, pb, "fp64")
+        torch.cuda.synchronize()
+    o = orc.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, 4)
+    check_grad(g, o, "fp64", "after ENOMEM")
+
+
 def test_nonfinite_input_is_flagged(gpu_ctx):
     import torch
     from paper_1907_04839_amd import lddmm
