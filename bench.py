@@ -396,6 +396,8 @@ def main():
                     help="registrations of the seeded Poisson stream for the serving leg (0: skip)")
     ap.add_argument("--flow-only", action="store_true",
                     help="time only the grid deformation (lddmm_flow) and print its record")
+    ap.add_argument("--rk4-only", action="store_true",
+                    help="time only the Runge-Kutta leg and print its record")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for rocprofv3 --pmc passes: a 256 MiB copy (calibration) and 2 steps")
     args = ap.parse_args()
@@ -416,6 +418,10 @@ def main():
     if args.flow_only:
         with lddmm.Context(0) as ctx:
             print(json.dumps(flow_leg(ctx, args.precision)), flush=True)
+        return
+    if args.rk4_only:
+        with lddmm.Context(0) as ctx:
+            print(json.dumps(rk4_leg(ctx, args.precision)), flush=True)
         return
     pb = workload(args.workload)
     p0 = momentum(pb)
