@@ -88,8 +88,8 @@ typedef enum { LDDMM_ENERGY_INITIAL = 0, LDDMM_ENERGY_FINAL = 1 } lddmm_energy;
  * forward and four backward, errors O(dt^4) instead of O(dt).  The gradients
  * are the exact adjoint of the stage equations, and the flow of points takes
  * the same stages.  The trajectory keeps the four stage states of every step
- * (4 T + 1 records; 4 s + 1 with checkpoints every s steps).  The server
- * takes EULER only. */
+ * (4 T + 1 records; 4 s + 1 with checkpoints every s steps).  A server
+ * takes the integrator of its configuration for every job. */
 typedef enum { LDDMM_EULER = 0, LDDMM_RK4 = 1 } lddmm_integrator;
 
 typedef struct {
@@ -216,6 +216,7 @@ typedef struct {
   int32_t T;                  /* Euler steps of every job, 1..2^20 */
   int32_t precision;          /* lddmm_precision of every job */
   size_t hbm_budget_bytes;    /* arena for job state, allocated at create */
+  int32_t integrator;         /* lddmm_integrator of every job (0: Euler steps) */
 } lddmm_server_config;
 
 typedef struct {

@@ -59,12 +59,14 @@ struct ServerJob {
 // Byte layout of one job inside its arena block.
 struct JobLayout {
   size_t q0, x, cen, st, ad, hp0, xc, h0p, out3, traj, arec, q1, vec, hist, state, out3a, q1a;
+  size_t rk_acc, rk_lam;
   size_t total;
 };
 
 size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 
-JobLayout job_layout(int n, int T, int precision, int m) {
+// spt: point records per step, 1 for Euler steps, 4 for Runge-Kutta stages.
+JobLayout job_layout(int n, int T, int precision, int m, int spt) {
   JobLayout L{};
   const size_t N = (size_t)n, m3 = 3 * N, rb = rec_bytes(precision), nb = (N + 63) / 64;
   size_t off = 0;
@@ -78,7 +80,7 @@ JobLayout job_layout(int n, int T, int precision, int m) {
   L.xc = take(m3 * 8);
   L.h0p = take(nb * 8);
   L.out3 = take(4 * 8);
-  L.traj = take((size_t)(T + 1) * N * rb);
+  L.traj = take(((size_t)spt * T + 1) * N * rb);
   L.arec = take(2 * N * rb);
   L.q1 = take(m3 * 8);
   L.vec = take(5 * m3 * 8);
@@ -86,6 +88,8 @@ JobLayout job_layout(int n, int T, int precision, int m) {
   L.state = take(sizeof(LbfgsState));
   L.out3a = take(4 * 8);
   L.q1a = take(m3 * 8);
+  L.rk_acc = take(spt == 4 ? 6 * N * 8 : 0);
+  L.rk_lam = take(spt == 4 ? 6 * N * 8 : 0);
   L.total = off;
   return L;
 }
@@ -193,7 +197,8 @@ void worker_fail(lddmm_server* s, hipError_t e, const char* what) {
 // initialises its optimiser (all enqueued on the server stream).
 bool admit(lddmm_server* s, ServerJob* j, int k) {
   const int n = j->p.n, T = s->cfg.T, mode = s->cfg.precision;
-  const JobLayout L = job_layout(n, T, mode, j->o.m);
+  const int spt = s->cfg.integrator == LDDMM_RK4 ? 4 : 1;
+  const JobLayout L = job_layout(n, T, mode, j->o.m, spt);
   void* base = static_cast<char*>(s->arena_base) + j->off;
   const size_t m3 = 3 * (size_t)n;
   double* q0 = at<double>(base, L.q0);
@@ -219,6 +224,9 @@ bool admit(lddmm_server* s, ServerJob* j, int k) {
   b.arec = at<void>(base, L.arec);
   b.q1 = at<double>(base, L.q1);
   b.flag = s->flag;
+  b.spt = spt;
+  b.rk_acc = at<double>(base, L.rk_acc);
+  b.rk_lam = at<double>(base, L.rk_lam);
 
   LbfgsJob lj{};
   lj.active = 1;
@@ -292,12 +300,17 @@ bool build_graph(lddmm_server* s) {
   const int mode = s->cfg.precision, T = s->cfg.T, M = s->cfg.max_slots;
   hipStream_t st = s->stream;
   W_TRY(s, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal), "capture");
+  // stages: 0 (one Euler launch per step) or the Runge-Kutta stages 1..4
+  const bool rk = s->cfg.integrator == LDDMM_RK4;
+  const int s0 = rk ? 1 : 0, s1 = rk ? 4 : 0;
   hipError_t e = launch_stage_batch(mode, s->d_jobs, M, s->cfg.max_n, st);
   for (int t = 0; t < T && e == hipSuccess; ++t)
-    e = launch_fwd_batch(mode, s->d_jobs, s->d_items, s->d_nitems, s->capacity, t, st);
+    for (int k = s0; k <= s1 && e == hipSuccess; ++k)
+      e = launch_fwd_batch(mode, s->d_jobs, s->d_items, s->d_nitems, s->capacity, t, k, st);
   if (e == hipSuccess) e = launch_loss_batch(mode, s->d_jobs, M, st);
   for (int t = T - 1; t >= 0 && e == hipSuccess; --t)
-    e = launch_adj_batch(mode, s->d_jobs, s->d_items, s->d_nitems, s->capacity, t, T, st);
+    for (int k = s1; k >= s0 && e == hipSuccess; --k)
+      e = launch_adj_batch(mode, s->d_jobs, s->d_items, s->d_nitems, s->capacity, t, k, T, st);
   if (e == hipSuccess) e = launch_lbfgs_step_batch(s->d_ljobs, M, st);
   if (e == hipSuccess) e = launch_gather_done(s->d_ljobs, M, s->d_done, st);
   hipGraph_t g = nullptr;
@@ -451,9 +464,10 @@ lddmm_status lddmm_server_job_footprint(const lddmm_server_config* cfg, int32_t 
                                         size_t* bytes) {
   if (!cfg || !bytes || n < 1 || n > (1 << 26) || m < 1 || m > kMaxHistory || cfg->T < 1 ||
       cfg->T > (1 << 20) ||
-      cfg->precision < LDDMM_FP32 || cfg->precision > LDDMM_FP64)
+      cfg->precision < LDDMM_FP32 || cfg->precision > LDDMM_FP64 ||
+      (cfg->integrator != LDDMM_EULER && cfg->integrator != LDDMM_RK4))
     return sfail(nullptr, LDDMM_EINVAL, "invalid footprint query");
-  *bytes = job_layout(n, cfg->T, cfg->precision, m).total;
+  *bytes = job_layout(n, cfg->T, cfg->precision, m, cfg->integrator == LDDMM_RK4 ? 4 : 1).total;
   return LDDMM_OK;
 }
 
@@ -463,6 +477,7 @@ lddmm_status lddmm_server_create(const lddmm_server_config* cfg, lddmm_server** 
   if (cfg->max_slots < 1 || cfg->max_slots > 1024 || cfg->max_n < 1 || cfg->max_n > (1 << 20) ||
       cfg->T < 1 || cfg->T > (1 << 20) || cfg->precision < LDDMM_FP32 ||
       cfg->precision > LDDMM_FP64 ||
+      (cfg->integrator != LDDMM_EULER && cfg->integrator != LDDMM_RK4) ||
       cfg->hbm_budget_bytes < 4096)
     return sfail(nullptr, LDDMM_EINVAL, "invalid server configuration");
   int count = 0;
@@ -537,8 +552,8 @@ lddmm_status lddmm_server_submit(lddmm_server* s, const lddmm_params* p,
   if (p->energy != LDDMM_ENERGY_INITIAL)
     return sfail(s, LDDMM_EINVAL, "the server takes the energy term at t = 0 only");
   if (p->dim == 2) return sfail(s, LDDMM_EINVAL, "the server solves 3D problems only");
-  if (p->integrator != LDDMM_EULER)
-    return sfail(s, LDDMM_EINVAL, "the server takes Euler steps only");
+  if (p->integrator != s->cfg.integrator)
+    return sfail(s, LDDMM_EINVAL, "the integrator must match the server's");
   if (!(p->sigma > 0.0) || !(p->lambda >= 0.0) || !std::isfinite(p->sigma) ||
       !std::isfinite(p->lambda))
     return sfail(s, LDDMM_EINVAL, "sigma must be > 0 and lambda >= 0");
@@ -552,7 +567,8 @@ lddmm_status lddmm_server_submit(lddmm_server* s, const lddmm_params* p,
   j->q0.assign(q0, q0 + m3);
   j->x.assign(target, target + m3);
   if (o->init == 2) j->p0in.assign(p0, p0 + m3);
-  j->footprint = job_layout(p->n, p->T, p->precision, o->m).total;
+  j->footprint =
+      job_layout(p->n, p->T, p->precision, o->m, p->integrator == LDDMM_RK4 ? 4 : 1).total;
   std::lock_guard<std::mutex> g(s->mu);
   if (s->failed) { delete j; return LDDMM_EDEVICE; }
   if (Arena::round_up(j->footprint) > s->arena.size()) {

@@ -157,10 +157,12 @@ struct BatchJob {
   const double* p0;         // [n][3] momentum to evaluate (the optimiser's trial point)
   const int* done;          // the job's optimiser has finished: skip it
   double *cen, *st, *ad, *hp0, *xc, *h0p, *out3;
-  void *traj, *arec;        // (T+1) point records, two adjoint record buffers
+  void *traj, *arec;        // (spt T + 1) point records, two adjoint record buffers
   double* q1;               // [n][3] q(1) of the latest evaluation
   double* grad;             // [n][3] gradient of the latest evaluation
   int* flag;                // non-finite flag
+  int spt;                  // records per step: 1 (Euler), 4 (Runge-Kutta stages)
+  double *rk_acc, *rk_lam;  // [6][n] each, Runge-Kutta steps only
 };
 
 // 8-wave workgroups: 7 % more solves per second than 16-wave ones on the
@@ -172,10 +174,12 @@ constexpr int kBatchWaves = 8;
 // (job, i-block) item; items beyond *nitems exit), loss max_slots.
 hipError_t launch_stage_batch(int mode, const BatchJob* jobs, int max_slots, int max_n,
                               hipStream_t s);
+// stage: 0 for an Euler step, else the Runge-Kutta stage (1..4) of step t;
+// every job of the batch takes steps of the same kind.
 hipError_t launch_fwd_batch(int mode, const BatchJob* jobs, const int2* items, const int* nitems,
-                            int capacity, int t, hipStream_t s);
+                            int capacity, int t, int stage, hipStream_t s);
 hipError_t launch_loss_batch(int mode, const BatchJob* jobs, int max_slots, hipStream_t s);
 hipError_t launch_adj_batch(int mode, const BatchJob* jobs, const int2* items, const int* nitems,
-                            int capacity, int t, int T, hipStream_t s);
+                            int capacity, int t, int stage, int T, hipStream_t s);
 
 }  // namespace lddmm

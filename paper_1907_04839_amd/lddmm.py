@@ -54,7 +54,7 @@ class SolveResult(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_slots", ctypes.c_int32),
                 ("max_n", ctypes.c_int32), ("T", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("hbm_budget_bytes", ctypes.c_size_t)]
+                ("hbm_budget_bytes", ctypes.c_size_t), ("integrator", ctypes.c_int32)]
 
 
 class JobTimes(ctypes.Structure):
@@ -363,10 +363,12 @@ class Context:
 
 
 def server_config(T: int, precision="fp32c", max_slots: int = 32, max_n: int = 8192,
-                  hbm_budget_bytes: int = 1 << 30, device: int = 0) -> ServerConfig:
+                  hbm_budget_bytes: int = 1 << 30, device: int = 0,
+                  integrator="euler") -> ServerConfig:
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    it = INTEGRATORS[integrator] if isinstance(integrator, str) else int(integrator)
     return ServerConfig(int(device), int(max_slots), int(max_n), int(T), prec,
-                        int(hbm_budget_bytes))
+                        int(hbm_budget_bytes), it)
 
 
 def job_footprint(cfg: ServerConfig, n: int, m: int = 5) -> int:
@@ -381,8 +383,9 @@ class Server:
     are host float64 [N,3] arrays; results come back as numpy arrays."""
 
     def __init__(self, T: int, precision="fp32c", max_slots: int = 32, max_n: int = 8192,
-                 hbm_budget_bytes: int = 1 << 30, device: int = 0):
-        self.cfg = server_config(T, precision, max_slots, max_n, hbm_budget_bytes, device)
+                 hbm_budget_bytes: int = 1 << 30, device: int = 0, integrator="euler"):
+        self.cfg = server_config(T, precision, max_slots, max_n, hbm_budget_bytes, device,
+                                 integrator)
         self.precision = precision
         h = _vp()
         rc = lib().lddmm_server_create(ctypes.byref(self.cfg), ctypes.byref(h))
@@ -400,7 +403,8 @@ class Server:
         q0 = np.ascontiguousarray(q0, dtype=np.float64)
         target = np.ascontiguousarray(target, dtype=np.float64)
         n = q0.shape[0]
-        prm = make_params(n, self.cfg.T, sigma, lam, self.cfg.precision)
+        prm = make_params(n, self.cfg.T, sigma, lam, self.cfg.precision,
+                          integrator=self.cfg.integrator)
         if p0 is not None:
             opts.setdefault("init", 2)
             p0 = np.ascontiguousarray(p0, dtype=np.float64)

@@ -152,7 +152,7 @@ def test_rk4_autograd_matches_oracle(orc_mt):
     assert rel_err(host(x.grad), o["grad_x"]) <= 1e-12
 
 
-def test_server_rejects_rk4():
+def test_euler_server_rejects_rk4_jobs():
     import ctypes
     from paper_1907_04839_amd import lddmm
     pb = synth.random_problem(1170, 50, T=12)

@@ -140,3 +140,58 @@ def test_served_result_matches_plain_solve_within_tolerance(gpu_ctx):
     torch.cuda.synchronize()
     assert abs(r["loss"] - s["loss"]) / s["loss"] < 1e-5
     assert r["iters"] == s["iters"]
+
+
+def test_rk4_server_matches_plain_rk4_solve():
+    """A server configured for Runge-Kutta steps: in FP64 its registrations take
+    lddmm_solve's RK4 iterates (the two split the pair sums differently, so
+    they agree to rounding), and in FP32 a job's result is bitwise the same
+    alone and in a mix."""
+    import torch
+    from paper_1907_04839_amd import lddmm
+    Tr = 4
+    jobs = [small_job(60 + j, n, iters=8) for j, n in enumerate([500, 1300])]
+    with lddmm.Server(Tr, "fp64", max_slots=4, max_n=4096, hbm_budget_bytes=256 << 20,
+                      integrator="rk4") as s:
+        ids = [s.submit(pb.q0, pb.target, pb.sigma, pb.lam, max_iter=pb.iters) for pb in jobs]
+        res = [s.result(i, timeout=120) for i in ids]
+    with lddmm.Context(0) as ctx:
+        for pb, r in zip(jobs, res):
+            ref = ctx.solve(torch.from_numpy(pb.q0).cuda(), torch.from_numpy(pb.target).cuda(),
+                            Tr, pb.sigma, pb.lam, "fp64", max_iter=pb.iters, integrator="rk4")
+            torch.cuda.synchronize()
+            el = abs(r["loss"] - ref["loss"]) / ref["loss"]
+            print(f"[serve rk4 fp64 n={pb.n}] iters {r['iters']}/{ref['iters']} loss {el:.2e}",
+                  flush=True)
+            assert r["iters"] == ref["iters"] and el < 1e-10
+    mix = [small_job(70 + j, n, iters=6) for j, n in enumerate([900, 200, 1700])]
+
+    def serve(batch):
+        with lddmm.Server(Tr, "fp32c", max_slots=8, max_n=4096, hbm_budget_bytes=256 << 20,
+                          integrator="rk4") as s:
+            ids = [s.submit(pb.q0, pb.target, pb.sigma, pb.lam, max_iter=pb.iters)
+                   for pb in batch]
+            return [s.result(i, timeout=120) for i in ids]
+    mixed = serve(mix)
+    for pb, m in zip(mix, mixed):
+        same(serve([pb])[0], m)
+
+
+def test_rk4_footprint_and_integrator_mismatch():
+    import ctypes
+    from paper_1907_04839_amd import lddmm
+    n = 1000
+    eu = lddmm.job_footprint(lddmm.server_config(T, "fp32c"), n)
+    rk = lddmm.job_footprint(lddmm.server_config(T, "fp32c", integrator="rk4"), n)
+    # 3 T more point records and two FP64 [6][N] accumulators
+    assert abs(rk - eu - (3 * T * n * 32 + 2 * 48 * n)) < 4 * 256
+    pb = small_job(80, 300)
+    with lddmm.Server(T, "fp32c", max_slots=2, max_n=1024, hbm_budget_bytes=64 << 20,
+                      integrator="rk4") as s:
+        prm = lddmm.make_params(pb.n, T, pb.sigma, pb.lam, "fp32c")   # Euler steps
+        o = lddmm.solve_opts("fp32c")
+        jid = ctypes.c_int64(0)
+        st = lddmm.lib().lddmm_server_submit(s._h, ctypes.byref(prm), ctypes.byref(o),
+                                              pb.q0.ctypes.data, pb.target.ctypes.data, None,
+                                              ctypes.byref(jid))
+        assert st == lddmm.EINVAL

@@ -36,6 +36,10 @@ def test_job_footprint_grows_with_n_and_T():
         lddmm.job_footprint(cfg, (1 << 26) + 1)
     with pytest.raises(lddmm.LddmmError):
         lddmm.job_footprint(lddmm.server_config((1 << 20) + 1, "fp32c"), 500)
+    with pytest.raises(lddmm.LddmmError):
+        lddmm.job_footprint(lddmm.server_config(40, "fp32c", integrator=2), 500)
+    rk = lddmm.job_footprint(lddmm.server_config(40, "fp32c", integrator="rk4"), 8000)
+    assert rk > b + 3 * 40 * 32 * 8000
 
 
 def test_auto_checkpoint_choice():
