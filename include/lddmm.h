@@ -94,7 +94,7 @@ typedef enum { LDDMM_EULER = 0, LDDMM_RK4 = 1 } lddmm_integrator;
 
 typedef struct {
   int32_t n;               /* landmarks, 1..2^26 */
-  int32_t T;               /* Euler steps, 1..2^20 (dt = 1/T) */
+  int32_t T;               /* time steps, 1..2^20 (dt = 1/T) */
   double sigma;            /* Gaussian kernel width (standard deviation), > 0 */
   double lambda;           /* mismatch weight, >= 0 */
   int32_t precision;       /* lddmm_precision */
@@ -128,7 +128,7 @@ lddmm_status lddmm_ctx_destroy(lddmm_ctx* ctx);
 lddmm_status lddmm_workspace_size(const lddmm_params* params, size_t* bytes);
 
 /* Forward shooting (Alg. 1, forward loop; eq. 2): integrates (q, p) from
- * (q0, p0) over T Euler steps.
+ * (q0, p0) over T steps of params->integrator (Euler by default).
  *   q0, p0 : in,  [n][3] device FP64
  *   q1, p1 : out, [n][3] device FP64, q(1) and p(1); either may be NULL
  *   H0     : out, device FP64 scalar H(q0,p0) (eq. 1); may be NULL
@@ -206,14 +206,15 @@ lddmm_status lddmm_solve(lddmm_ctx* ctx, const lddmm_params* params, const lddmm
  * hipGraph; jobs join at the next round after admission and leave when their
  * optimiser finishes.  A job's result does not depend on the other jobs in
  * the batch (same decomposition, same summation order).  All jobs of a
- * server share T and the precision. */
+ * server share T, the precision and the integrator; the server solves 3D
+ * problems with the energy term at t = 0. */
 typedef struct lddmm_server lddmm_server;
 
 typedef struct {
   int32_t device;
   int32_t max_slots;          /* jobs on the GPU at once, 1..1024 */
   int32_t max_n;              /* largest n accepted, 1..2^20 */
-  int32_t T;                  /* Euler steps of every job, 1..2^20 */
+  int32_t T;                  /* time steps of every job, 1..2^20 */
   int32_t precision;          /* lddmm_precision of every job */
   size_t hbm_budget_bytes;    /* arena for job state, allocated at create */
   int32_t integrator;         /* lddmm_integrator of every job (0: Euler steps) */
