@@ -338,8 +338,12 @@ lddmm_status lddmm_ctx_timing(lddmm_ctx* ctx, lddmm_timing* out, int reset);
 /* Static description of a status code; never NULL. */
 const char* lddmm_status_string(lddmm_status status);
 
-/* Detail of the last error reported by a call on ctx from this thread
- * (empty string if none); with ctx == NULL, of the last context-free error. */
+/* Detail of the last error reported by a call on ctx (empty string if none;
+ * calls on one context are serialised by the caller, so this is the error
+ * of the latest such call that failed).  With ctx == NULL: the detail of the
+ * last error this thread got from a call made without a usable context.
+ * The string stays valid until the next failing call on the same context
+ * (or, for ctx == NULL, in the same thread). */
 const char* lddmm_last_error(lddmm_ctx* ctx);
 
 /* Library version, "major.minor.patch". */
