@@ -315,10 +315,11 @@ lddmm_status lddmm_flow(lddmm_ctx* ctx, const lddmm_params* params, const double
 lddmm_status lddmm_ctx_check(lddmm_ctx* ctx, void* stream);
 
 /* Per-kernel timing, for benchmarks.  While enabled, every launch of the
- * forward and of the adjoint pair-sum kernel and of the point-flow kernel is
- * bracketed by two HIP events
- * recorded on the call's stream (the stream the kernel runs on); durations
- * accumulate until read.  Off by default.  Errors: EINVAL. */
+ * forward and of the adjoint pair-sum kernel and of the point-flow kernel
+ * carries two HIP events of the call's stream (the stream the kernel runs
+ * on), tied by hipExtLaunchKernel to the start and the end of the kernel's
+ * execution; durations accumulate until read.  The results are the same as
+ * with timing off.  Off by default.  Errors: EINVAL. */
 typedef struct {
   double fwd_ms;           /* summed duration of forward pair-kernel launches */
   double adj_ms;           /* summed duration of adjoint pair-kernel launches */

@@ -346,7 +346,7 @@ class Context:
         return r
 
     def set_timing(self, enable: bool) -> None:
-        """Bracket every pair-kernel launch with HIP events on its stream."""
+        """Time every pair-kernel and point-flow launch with HIP events tied to the kernel."""
         _check(lib().lddmm_ctx_set_timing(self._h, int(bool(enable))), self._h)
 
     def timing(self, reset: bool = True) -> dict:
