@@ -469,3 +469,29 @@ def test_zero_lambda_gradient_is_Hp0(gpu_ctx, orc_mt, mode):
     eg = rel_err(host(r.grad), Hp)
     assert eg < TOL[mode] and abs(r.loss.item() - H) < TOL[mode] * H
     assert r.loss.item() == r.H0.item()
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_coincident_landmarks(gpu_ctx, orc_mt, mode):
+    """Duplicated landmarks (same q0, p0 and target; the pair has Delta = 0 and
+    g = 1 off the diagonal) match the oracle, and each copy's q(1) and gradient
+    equal the original's bitwise: both see the same data in the same order."""
+    rng = np.random.default_rng(1303)
+    base = synth.random_problem(1303, 700, T=4)
+    dup = rng.choice(700, size=130, replace=False)
+    src = np.concatenate([np.arange(700), dup])
+    perm = rng.permutation(src.size)       # copies land in other i-blocks and j-chunks
+    idx = src[perm]
+    q0, p0, x = (np.ascontiguousarray(a[idx]) for a in (base.q0, base.p0, base.target))
+    pb = synth.Problem("coincident830", q0, x, p0, base.sigma, base.lam, base.T)
+    g = run_grad(gpu_ctx, pb, mode)
+    o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, pb.T)
+    check_grad(g, o, mode, "coincident")
+    pos = {}
+    for k, s in enumerate(idx):
+        pos.setdefault(int(s), []).append(k)
+    pairs = [(v[0], v[1]) for v in pos.values() if len(v) == 2]
+    assert len(pairs) == 130
+    a, b = np.array(pairs).T
+    assert np.array_equal(g["q1"][a], g["q1"][b])
+    assert np.array_equal(g["grad"][a], g["grad"][b])
