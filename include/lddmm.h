@@ -107,7 +107,7 @@ typedef struct {
                               leave the z terms out (about 30 % fewer
                               instructions per pair) and every z output is 0.
                               Inputs with a non-zero z give undefined results.
-                              The server solves 3D problems only. */
+                              A server takes planar and 3D jobs side by side. */
   int32_t integrator;      /* lddmm_integrator (0: Euler steps) */
 } lddmm_params;
 
@@ -206,8 +206,8 @@ lddmm_status lddmm_solve(lddmm_ctx* ctx, const lddmm_params* params, const lddmm
  * hipGraph; jobs join at the next round after admission and leave when their
  * optimiser finishes.  A job's result does not depend on the other jobs in
  * the batch (same decomposition, same summation order).  All jobs of a
- * server share T, the precision and the integrator; the server solves 3D
- * problems with the energy term at t = 0. */
+ * server share T, the precision and the integrator; each job may be planar
+ * (lddmm_params.dim = 2) or 3D, and takes the energy term at t = 0. */
 typedef struct lddmm_server lddmm_server;
 
 typedef struct {

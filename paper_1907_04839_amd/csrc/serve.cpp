@@ -8,7 +8,9 @@
 // and one optimiser step per round, as one replay of a captured hipGraph:
 // batched stage, T forward pair-sum launches, batched loss, T adjoint
 // launches, batched L-BFGS step.  Each pair-sum launch covers every
-// (job, 64-landmark i-block) item, so small jobs share the chip instead of
+// (job, 64-landmark i-block) item of its kind (once planar jobs have come,
+// each step has a launch for the 3D items and one for the planar items,
+// which leave the z terms out), so small jobs share the chip instead of
 // leaving it idle.  Jobs join at the next round after admission and leave
 // when their optimiser finishes; finished jobs are skipped on the device, so
 // nothing is wasted while the host notices.
@@ -135,6 +137,10 @@ struct lddmm_server {
   bool tables_dirty = true;
 
   hipGraphExec_t graph = nullptr;
+  // Pair-kernel instances the graph launches per step: bit 0 for 3D jobs, bit 1
+  // for planar jobs.  dims_seen grows as jobs of each kind are admitted; the
+  // graph is captured again when it has grown (at most twice per server).
+  int graph_dims = 0, dims_seen = 0;
 
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -191,6 +197,13 @@ void worker_fail(lddmm_server* s, hipError_t e, const char* what) {
   do {                                                     \
     hipError_t e_ = (expr);                                \
     if (e_ != hipSuccess) { worker_fail(s, e_, what); return false; } \
+  } while (0)
+
+// The same in a function that returns nothing.
+#define W_TRY_V(s, expr, what)                             \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) { worker_fail(s, e_, what); return; } \
   } while (0)
 
 // Puts a queued job into slot k: copies its inputs, centres them, and
@@ -269,16 +282,22 @@ bool admit(lddmm_server* s, ServerJob* j, int k) {
 
 bool upload_tables(lddmm_server* s, int parity) {
   const int M = s->cfg.max_slots;
-  std::vector<int> order;
-  for (int k = 0; k < M; ++k)
-    if (s->tab[k].active) order.push_back(k);
-  // largest jobs first, so their i-blocks are dispatched first
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return s->tab[a].n > s->tab[b].n; });
+  // items of 3D jobs first, then those of planar jobs (each group has its own
+  // pair-kernel launch); within a group the largest jobs first, so their
+  // i-blocks are dispatched first
   int ni = 0;
-  for (int k : order)
-    for (int ib = 0; ib < s->tab[k].nb; ++ib) s->h_items[parity][ni++] = make_int2(k, ib);
-  *s->h_nitems[parity] = ni;
+  for (int dim : {3, 2}) {
+    std::vector<int> order;
+    for (int k = 0; k < M; ++k)
+      if (s->tab[k].active && (s->slot_job[k]->p.dim == 2 ? 2 : 3) == dim) order.push_back(k);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return s->tab[a].n > s->tab[b].n; });
+    const int first = ni;
+    for (int k : order)
+      for (int ib = 0; ib < s->tab[k].nb; ++ib) s->h_items[parity][ni++] = make_int2(k, ib);
+    s->h_nitems[parity][dim == 3 ? 0 : 1] = ni - first;
+    if (ni > first) s->dims_seen |= dim == 3 ? 1 : 2;
+  }
   std::memcpy(s->h_jobs[parity], s->tab.data(), sizeof(BatchJob) * M);
   std::memcpy(s->h_ljobs[parity], s->ltab.data(), sizeof(LbfgsJob) * M);
   hipStream_t st = s->stream;
@@ -289,8 +308,8 @@ bool upload_tables(lddmm_server* s, int parity) {
   if (ni > 0)
     W_TRY(s, hipMemcpyAsync(s->d_items, s->h_items[parity], sizeof(int2) * ni,
                             hipMemcpyHostToDevice, st), "table copy");
-  W_TRY(s, hipMemcpyAsync(s->d_nitems, s->h_nitems[parity], sizeof(int), hipMemcpyHostToDevice,
-                          st), "table copy");
+  W_TRY(s, hipMemcpyAsync(s->d_nitems, s->h_nitems[parity], 2 * sizeof(int),
+                          hipMemcpyHostToDevice, st), "table copy");
   s->tables_dirty = false;
   return true;
 }
@@ -303,14 +322,21 @@ bool build_graph(lddmm_server* s) {
   // stages: 0 (one Euler launch per step) or the Runge-Kutta stages 1..4
   const bool rk = s->cfg.integrator == LDDMM_RK4;
   const int s0 = rk ? 1 : 0, s1 = rk ? 4 : 0;
+  const int dims = s->dims_seen;
   hipError_t e = launch_stage_batch(mode, s->d_jobs, M, s->cfg.max_n, st);
   for (int t = 0; t < T && e == hipSuccess; ++t)
     for (int k = s0; k <= s1 && e == hipSuccess; ++k)
-      e = launch_fwd_batch(mode, s->d_jobs, s->d_items, s->d_nitems, s->capacity, t, k, st);
+      for (int d : {3, 2})
+        if (e == hipSuccess && (dims & (d == 3 ? 1 : 2)))
+          e = launch_fwd_batch(mode, d, s->d_jobs, s->d_items, s->d_nitems, s->capacity, t, k,
+                               st);
   if (e == hipSuccess) e = launch_loss_batch(mode, s->d_jobs, M, st);
   for (int t = T - 1; t >= 0 && e == hipSuccess; --t)
     for (int k = s1; k >= s0 && e == hipSuccess; --k)
-      e = launch_adj_batch(mode, s->d_jobs, s->d_items, s->d_nitems, s->capacity, t, k, T, st);
+      for (int d : {3, 2})
+        if (e == hipSuccess && (dims & (d == 3 ? 1 : 2)))
+          e = launch_adj_batch(mode, d, s->d_jobs, s->d_items, s->d_nitems, s->capacity, t, k,
+                               T, st);
   if (e == hipSuccess) e = launch_lbfgs_step_batch(s->d_ljobs, M, st);
   if (e == hipSuccess) e = launch_gather_done(s->d_ljobs, M, s->d_done, st);
   hipGraph_t g = nullptr;
@@ -320,6 +346,7 @@ bool build_graph(lddmm_server* s) {
   e = hipGraphInstantiate(&s->graph, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) { worker_fail(s, e, "graph instantiate"); return false; }
+  s->graph_dims = dims;
   return true;
 }
 
@@ -424,6 +451,13 @@ void worker_main(lddmm_server* s) {
     if (s->n_running > 0) {
       const int par = (int)(r & 1);
       if (s->tables_dirty && !upload_tables(s, par)) return;
+      if (s->graph && s->graph_dims != s->dims_seen) {
+        // a job of a new kind: capture a graph that also launches its pair kernels
+        // (the old one may still run: wait for it before destroying it)
+        W_TRY_V(s, hipStreamSynchronize(s->stream), "graph rebuild");
+        (void)hipGraphExecDestroy(s->graph);
+        s->graph = nullptr;
+      }
       if (!s->graph && !build_graph(s)) return;
       hipError_t e = hipGraphLaunch(s->graph, s->stream);
       if (e == hipSuccess)
@@ -522,7 +556,7 @@ lddmm_status lddmm_server_create(const lddmm_server_config* cfg, lddmm_server** 
     // empty tables until the first admission
     e = hipMemsetAsync(s->d_jobs, 0, sizeof(BatchJob) * M, s->stream);
     if (e == hipSuccess) e = hipMemsetAsync(s->d_ljobs, 0, sizeof(LbfgsJob) * M, s->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(s->d_nitems, 0, sizeof(int), s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(s->d_nitems, 0, 2 * sizeof(int), s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   }
   if (e != hipSuccess) {
@@ -551,7 +585,8 @@ lddmm_status lddmm_server_submit(lddmm_server* s, const lddmm_params* p,
     return sfail(s, LDDMM_EINVAL, "T and precision must match the server's");
   if (p->energy != LDDMM_ENERGY_INITIAL)
     return sfail(s, LDDMM_EINVAL, "the server takes the energy term at t = 0 only");
-  if (p->dim == 2) return sfail(s, LDDMM_EINVAL, "the server solves 3D problems only");
+  if (p->dim != 0 && p->dim != 2 && p->dim != 3)
+    return sfail(s, LDDMM_EINVAL, "dim must be 2 or 3");
   if (p->integrator != s->cfg.integrator)
     return sfail(s, LDDMM_EINVAL, "the integrator must match the server's");
   if (!(p->sigma > 0.0) || !(p->lambda >= 0.0) || !std::isfinite(p->sigma) ||

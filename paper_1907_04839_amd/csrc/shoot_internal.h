@@ -145,7 +145,8 @@ hipError_t launch_forward_out(int n, int nb, const double* st, const double* cen
                               hipStream_t s);
 
 // One registration of a batched launch, as the batched kernels see it.  All
-// jobs of a batch share T and the precision; the decomposition of every job
+// jobs of a batch share T, the precision and the kind of step; planar and 3D
+// jobs have pair kernels of their own.  The decomposition of every job
 // is one workgroup of kBatchWaves waves per 64-landmark i-block and no j split, so a
 // job's results do not depend on which other jobs share the launch.
 struct BatchJob {
@@ -171,15 +172,18 @@ constexpr int kBatchWaves = 8;
 
 // Launch shapes of a batch of at most max_slots jobs with n <= max_n:
 // stage (max_n/256, max_slots), pair kernels `capacity` workgroups (one per
-// (job, i-block) item; items beyond *nitems exit), loss max_slots.
+// (job, i-block) item), loss max_slots.  items holds nitems[0] items of 3D
+// jobs followed by nitems[1] items of planar jobs; the pair launch for dim 3
+// (or 2) takes its group, and its workgroups beyond the group's count exit.
 hipError_t launch_stage_batch(int mode, const BatchJob* jobs, int max_slots, int max_n,
                               hipStream_t s);
 // stage: 0 for an Euler step, else the Runge-Kutta stage (1..4) of step t;
 // every job of the batch takes steps of the same kind.
-hipError_t launch_fwd_batch(int mode, const BatchJob* jobs, const int2* items, const int* nitems,
-                            int capacity, int t, int stage, hipStream_t s);
+hipError_t launch_fwd_batch(int mode, int dim, const BatchJob* jobs, const int2* items,
+                            const int* nitems, int capacity, int t, int stage, hipStream_t s);
 hipError_t launch_loss_batch(int mode, const BatchJob* jobs, int max_slots, hipStream_t s);
-hipError_t launch_adj_batch(int mode, const BatchJob* jobs, const int2* items, const int* nitems,
-                            int capacity, int t, int stage, int T, hipStream_t s);
+hipError_t launch_adj_batch(int mode, int dim, const BatchJob* jobs, const int2* items,
+                            const int* nitems, int capacity, int t, int stage, int T,
+                            hipStream_t s);
 
 }  // namespace lddmm

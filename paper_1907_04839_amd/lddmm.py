@@ -398,12 +398,14 @@ class Server:
         raise LddmmError(rc, lib().lddmm_server_last_error(self._h).decode()
                          or lib().lddmm_status_string(rc).decode())
 
-    def submit(self, q0, target, sigma: float, lam: float, p0=None, **opts) -> int:
+    def submit(self, q0, target, sigma: float, lam: float, p0=None, dim: int = 3,
+               **opts) -> int:
+        """Queue one registration; ``dim=2`` for a planar job (every z is 0)."""
         import numpy as np
         q0 = np.ascontiguousarray(q0, dtype=np.float64)
         target = np.ascontiguousarray(target, dtype=np.float64)
         n = q0.shape[0]
-        prm = make_params(n, self.cfg.T, sigma, lam, self.cfg.precision,
+        prm = make_params(n, self.cfg.T, sigma, lam, self.cfg.precision, dim=dim,
                           integrator=self.cfg.integrator)
         if p0 is not None:
             opts.setdefault("init", 2)

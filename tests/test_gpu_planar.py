@@ -69,12 +69,54 @@ def test_planar_solve_equals_3d(gpu_ctx):
     assert a["loss"] == b["loss"] and a["iters"] == b["iters"] and a["fevals"] == b["fevals"]
 
 
-def test_server_rejects_planar_problems():
+def test_server_takes_planar_jobs_beside_3d_ones():
+    """Planar jobs (dim = 2) in a server that also runs 3D jobs: each gives bitwise
+    the result of the same job run as 3D (the z terms it leaves out are exact
+    zeros), keeps every z component of p0 at 0, and in FP64 takes the iterates of
+    lddmm_solve on the planar problem."""
+    import torch
+    from paper_1907_04839_amd import lddmm
+    Tp, iters = 12, 8
+    flat = [synth.planar(synth.random_problem(1260 + j, n, T=Tp))
+            for j, n in enumerate([50, 700, 1300])]
+    solid = [synth.random_problem(1270 + j, n, T=Tp) for j, n in enumerate([400, 900])]
+
+    def serve(batch, precision="fp32c"):
+        with lddmm.Server(Tp, precision, max_slots=8, max_n=2048,
+                          hbm_budget_bytes=256 << 20) as s:
+            ids = [s.submit(pb.q0, pb.target, pb.sigma, pb.lam, dim=d, max_iter=iters)
+                   for pb, d in batch]
+            return [s.result(i, timeout=120) for i in ids]
+
+    mixed = serve([(pb, 2) for pb in flat] + [(pb, 3) for pb in solid])
+    as_3d = serve([(pb, 3) for pb in flat])
+    for pb, m, r in zip(flat, mixed, as_3d):
+        print(f"[serve planar n={pb.n}] iters {m['iters']} loss {m['loss']:.6e}", flush=True)
+        assert np.all(m["p0"][:, 2] == 0.0)
+        np.testing.assert_array_equal(m["p0"], r["p0"])
+        for k in ("loss", "H0", "mismatch", "iters", "fevals", "status"):
+            assert m[k] == r[k], k
+    alone = serve([(solid[1], 3)])[0]
+    np.testing.assert_array_equal(mixed[-1]["p0"], alone["p0"])
+
+    pb = flat[1]
+    got = serve([(pb, 2)], "fp64")[0]
+    with lddmm.Context(0) as ctx:
+        ref = ctx.solve(to_dev(pb.q0), to_dev(pb.target), Tp, pb.sigma, pb.lam, "fp64", dim=2,
+                        max_iter=iters)
+        torch.cuda.synchronize()
+    el = abs(got["loss"] - ref["loss"]) / ref["loss"]
+    print(f"[serve planar fp64] iters {got['iters']}/{ref['iters']} loss {el:.2e}", flush=True)
+    assert got["iters"] == ref["iters"] and el < 1e-10
+    assert rel_err(got["p0"], host(ref["p0"])) < 1e-9
+
+
+def test_server_rejects_an_unknown_dim():
     import ctypes
     from paper_1907_04839_amd import lddmm
-    pb = synth.planar(synth.random_problem(1260, 50, T=12))
+    pb = synth.planar(synth.random_problem(1261, 50, T=12))
     with lddmm.Server(12, "fp32c", max_slots=2, max_n=1024, hbm_budget_bytes=64 << 20) as s:
-        prm = lddmm.make_params(pb.n, 12, pb.sigma, pb.lam, "fp32c", dim=2)
+        prm = lddmm.make_params(pb.n, 12, pb.sigma, pb.lam, "fp32c", dim=4)
         o = lddmm.solve_opts("fp32c")
         jid = ctypes.c_int64(0)
         st = lddmm.lib().lddmm_server_submit(s._h, ctypes.byref(prm), ctypes.byref(o),
