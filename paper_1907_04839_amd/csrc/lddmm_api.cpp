@@ -102,6 +102,12 @@ int target_waves() {
   return v;
 }
 
+// Tuning runs that set the plan through the environment get that plan as is.
+bool plan_overridden() {
+  static const bool v = std::getenv("LDDMM_TARGET_WAVES") || std::getenv("LDDMM_MAX_WG_WAVES");
+  return v;
+}
+
 lddmm_status fail(lddmm_ctx* ctx, lddmm_status st, const char* fmt, ...)
     __attribute__((format(printf, 3, 4)));
 
@@ -245,6 +251,7 @@ Job make_job(const lddmm_params& p, void* ws) {
   Job j{};
   j.p = p;
   j.plan = make_plan(p.n, target_waves());
+  if (!plan_overridden()) widen_plan(j.plan, p.precision, p.integrator == LDDMM_RK4);
   j.sc = make_scales(p.sigma, p.T);
   j.L = make_layout(p, j.plan);
   j.ws = ws;
@@ -317,7 +324,7 @@ hipError_t run_adjoint(const Job& j, int t0, int t1, int* cur, double* grad, hip
     for (int st = stages - 1; st >= 0; --st) {
       AdjArgs a{};
       a.n = j.p.n; a.nb = j.plan.nb; a.S = j.plan.S; a.chunk = j.plan.chunk;
-      a.wchunk = j.plan.wchunk;
+      a.wchunk = j.plan.wchunk_a;
       a.dim = j.dim;
       a.rk = stages == 4 ? st + 1 : 0;
       a.rk_lam = j.rk_lam;

@@ -20,12 +20,19 @@ struct Plan {
   int n;        // landmarks
   int nb;       // i-blocks of 64
   int S;        // j-chunks (workgroups) per i-block
-  int W;        // waves per workgroup
+  int W;        // waves per workgroup of the forward pair kernel
   int chunk;    // j per workgroup
-  int wchunk;   // j per wave
+  int wchunk;   // j per wave of the forward pair kernel
+  int Wa;       // waves per workgroup of the adjoint pair kernel
+  int wchunk_a; // j per wave of the adjoint pair kernel
 };
 
 Plan make_plan(int n, int target_waves);
+
+// The workgroup widths measured fastest for the pair kernels of a precision
+// mode and kind of step (rk: Runge-Kutta stages), applied to the plans of 8
+// waves and 8 j-chunks; other plans are left as they are.
+void widen_plan(Plan& p, int mode, bool rk);
 
 // Coordinates enter the pair kernels pre-scaled by k = sqrt(log2(e) / (2 sigma^2)),
 // so that the kernel value is exp2(-|k q_i - k q_j|^2).
