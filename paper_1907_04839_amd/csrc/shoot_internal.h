@@ -154,7 +154,7 @@ hipError_t launch_forward_out(int n, int nb, const double* st, const double* cen
 // One registration of a batched launch, as the batched kernels see it.  All
 // jobs of a batch share T, the precision and the kind of step; planar and 3D
 // jobs have pair kernels of their own.  The decomposition of every job
-// is one workgroup of kBatchWaves waves per 64-landmark i-block and no j split, so a
+// is one workgroup of batch_waves waves per 64-landmark i-block and no j split, so a
 // job's results do not depend on which other jobs share the launch.
 struct BatchJob {
   int active;               // the slot holds a job
@@ -173,9 +173,13 @@ struct BatchJob {
   double *rk_acc, *rk_lam;  // [6][n] each, Runge-Kutta steps only
 };
 
-// 8-wave workgroups: 7 % more solves per second than 16-wave ones on the
-// 48-job serving stream (14.9 vs 13.8), with lower p50 and p99 latency.
-constexpr int kBatchWaves = 8;
+// Waves per workgroup of the batched pair kernels.  On the 48-job serving
+// stream (FP32-compensated, Euler steps) 12-wave workgroups gave 15.7 solves/s
+// against 14.9 for 8-wave and 13.8 for 16-wave ones: two 12-wave workgroups
+// fill the 24 wave slots per CU that the adjoint's registers leave.  FP32,
+// FP64 and Runge-Kutta stage instances keep 8 (their registers differ; 12 was
+// measured only in the FP32-compensated Euler case).
+constexpr int batch_waves(bool compensated, bool rk) { return compensated && !rk ? 12 : 8; }
 
 // Launch shapes of a batch of at most max_slots jobs with n <= max_n:
 // stage (max_n/256, max_slots), pair kernels `capacity` workgroups (one per
