@@ -31,7 +31,7 @@ Plan make_plan(int n, int target_waves);
 
 // The workgroup widths measured fastest for the pair kernels of a precision
 // mode and kind of step (rk: Runge-Kutta stages), applied to the plans of 8
-// waves and 8, 4 or 2 j-chunks; other plans are left as they are.
+// waves and 8, 4, 3 or 2 j-chunks; other plans are left as they are.
 void widen_plan(Plan& p, int mode, bool rk);
 
 // Coordinates enter the pair kernels pre-scaled by k = sqrt(log2(e) / (2 sigma^2)),
