@@ -6,9 +6,13 @@ staging, T forward Euler steps of pair sums, the loss, and T adjoint steps of
 pair sums (Alg. 1 ComputeGradient).  It counts 2 T N^2 pair interactions
 (T N^2 forward + T N^2 adjoint); checkpoint recompute is not counted.
 
-Default workload: 4096 landmarks on a noisy ellipsoid (semi-axes 60/40/30)
-matched to an RK4-warped copy, sigma 8, lambda 1, T = 40, FP32 pair sums with
-64-pair tiles folded into FP64 (FP64 state, loss and adjoint state).
+Headline workload (`value`): the largest single-GPU configuration, 65536
+landmarks in two Gaussian blobs (centres 50 apart, sd 15), sigma 5, lambda 1,
+T = 50, FP32 pair sums with 64-pair tiles folded into FP64 (FP64 state, loss
+and adjoint state).  The same line carries the other precision modes at that
+size, the 4096-landmark ellipsoid registration (T = 40) with its full solve,
+the 16384-landmark sphere with checkpoints, the point flow, planar and
+Runge-Kutta legs, the serving stream, and the oracle timed on the host.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -91,7 +95,7 @@ def time_steps(ctx, dev, pb, precision, steps, warmup, ckpt_every=0, dim=3, inte
     return dt, float(out["out3"][0])
 
 
-def step_event_times(ctx, dev, pb, precision, steps):
+def step_event_times(ctx, dev, pb, precision, steps, ckpt_every=0):
     """Each evaluation bracketed by its own pair of events on the launch stream:
     per-step median and minimum in ms."""
     import statistics
@@ -103,7 +107,7 @@ def step_event_times(ctx, dev, pb, precision, steps):
     for a, b in evs:
         a.record()
         ctx.shoot_grad(q0, p0, x, pb.T, pb.sigma, pb.lam, precision=precision, want_q1=False,
-                       out=out)
+                       out=out, ckpt_every=ckpt_every)
         b.record()
     torch.cuda.synchronize()
     ms = [a.elapsed_time(b) for a, b in evs]
@@ -124,17 +128,95 @@ def kernel_times(ctx, dev, pb, precision, steps, ckpt_every=0, dim=3, integrator
                 fwd_launches=t["fwd_launches"], adj_launches=t["adj_launches"])
 
 
+# Issue rates measured on the chip by the probes of librate_probe.so (filled by
+# measured_ceilings(); empty when the probes did not run).
+CEILINGS: dict = {}
+
+
+def measured_ceilings(iters: int = 40000, reps: int = 5) -> dict:
+    """Lane-operations per second of plain instructions, 8 waves per SIMD of the
+    chip (2048 workgroups of 256 threads, 8 independent chains per lane): FP32 FMA
+    with VGPR operands and with one SGPR operand, v_exp_f32, FP64 FMA, FP32
+    multiply.  FMA rates are also given in TFLOP/s (2 flops each)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_1907_04839_amd", "librate_probe.so")
+    lib = ctypes.CDLL(path)
+    lib.rate_probe_run.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(ctypes.c_double)]
+    lib.rate_probe_run.restype = ctypes.c_int
+    names = ["fp32_fma_vgpr", "fp32_fma_sgpr", "exp_f32", "fp64_fma", "fp32_mul_vgpr"]
+    out = {}
+    for kind, name in enumerate(names):
+        r = ctypes.c_double(0.0)
+        rc = lib.rate_probe_run(kind, 2048, iters, reps, ctypes.byref(r))
+        if rc != 0:
+            raise RuntimeError(f"rate probe {name} failed: hipError {rc}")
+        out[name + "_per_s"] = round(r.value, 1)
+    for name in ("fp32_fma_vgpr", "fp32_fma_sgpr", "fp64_fma"):
+        out[name + "_tflops"] = round(2 * out[name + "_per_s"] / 1e12, 2)
+    # in units of one wave64 instruction per SIMD every 4 cycles (256 CUs, 2.4 GHz)
+    unit = 256 * 4 * 64 / 4 * 2.4e9
+    out["per_quad_cycle"] = {n: round(out[n + "_per_s"] / unit, 3) for n in names}
+    log("[bench] measured rates (per SIMD quad-cycle): " +
+        " ".join(f"{k}={v}" for k, v in out["per_quad_cycle"].items()))
+    return out
+
+
 def roofline(n, kt, traffic=None, precision="fp32c", flops=FLOPS_PER_PAIR):
     kind = "adj" if kt["adj_us"] >= kt["fwd_us"] else "fwd"
     dur = kt[f"{kind}_us"] * 1e-6
     pairs = float(n) * n
     achieved = flops[kind] * pairs / dur / 1e12
     issue_frac = VALU_PER_PAIR[kind] * pairs / dur / PEAK_VALU_INSTR_PER_S
-    return {"bound": "alu", "kernel": f"{kind}_pair", "achieved": round(achieved, 3),
-            "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
-            "frac": round(achieved / PEAK_TFLOPS[precision], 4), "traffic": traffic,
-            "avg_launch_us": round(kt[f"{kind}_us"], 2),
-            "valu_issue_frac": round(issue_frac, 4)}
+    out = {"bound": "alu", "kernel": f"{kind}_pair", "achieved": round(achieved, 3),
+           "peak": PEAK_TFLOPS[precision], "unit": "TFLOP/s",
+           "frac": round(achieved / PEAK_TFLOPS[precision], 4), "traffic": traffic,
+           "avg_launch_us": round(kt[f"{kind}_us"], 2),
+           "valu_issue_frac": round(issue_frac, 4)}
+    if CEILINGS:
+        # beside the published (packed) peak: the measured rate of plain FMAs with
+        # VGPR operands, and the kernel's one exp per pair against the measured
+        # v_exp_f32 rate
+        key = "fp64_fma_tflops" if precision == "fp64" else "fp32_fma_vgpr_tflops"
+        out["measured_fma_tflops"] = CEILINGS[key]
+        out["frac_of_measured_fma"] = round(achieved / CEILINGS[key], 4)
+        if precision != "fp64":
+            out["trans_frac"] = round(pairs / dur / CEILINGS["exp_f32_per_s"], 4)
+    return out
+
+
+def measure(ctx, name: str, precision: str, steps: int, warmup: int, ckpt_every: int = 0,
+            events: bool = True):
+    """pair-interactions/s of one workload (steps timed after warmup), per-step
+    event times, the pair kernels' average launch times, the roofline of the
+    dominant kernel and the whole evaluation's algorithmic ALU fraction."""
+    import torch
+    pb = workload(name)
+    dev = {k: torch.from_numpy(v).cuda() for k, v in
+           (("q0", pb.q0), ("x", pb.target), ("p0", momentum(pb)))}
+    pairs = 2 * pb.T * pb.n ** 2
+    dt, loss = time_steps(ctx, dev, pb, precision, steps, warmup, ckpt_every)
+    ms = 1e3 * dt / steps
+    out = {"workload": f"{pb.name}: N={pb.n} landmarks, T={pb.T} Euler steps, sigma={pb.sigma:g}, "
+                       f"lambda={pb.lam:g}" + (f", checkpoints every {ckpt_every}" if ckpt_every else ""),
+           "n": pb.n, "T": pb.T, "ckpt_every": ckpt_every, "precision": precision,
+           "pairs_per_step": pairs, "pairs_per_s": round(pairs * steps / dt, 1),
+           "ms_per_step": round(ms, 4), "loss": loss}
+    if events:
+        med, mn = step_event_times(ctx, dev, pb, precision, steps, ckpt_every)
+        out["ms_per_step_events"] = {"median": round(med, 4), "min": round(mn, 4)}
+    kt = kernel_times(ctx, dev, pb, precision, max(1, min(steps, 20)), ckpt_every)
+    out["kernel_us"] = {"fwd": round(kt["fwd_us"], 2), "adj": round(kt["adj_us"], 2)}
+    out["roofline"] = roofline(pb.n, kt, measured_traffic(name, precision), precision)
+    # the whole evaluation against the same peak: every forward and adjoint pair's
+    # algorithmic flops (recompute launches not counted) over the step time
+    flops = (FLOPS_PER_PAIR["fwd"] + FLOPS_PER_PAIR["adj"]) * pb.T * float(pb.n) ** 2
+    out["whole_eval_alu_frac"] = round(flops / (ms * 1e-3) / (PEAK_TFLOPS[precision] * 1e12), 4)
+    log(f"[bench] {pb.name} {precision}: {out['pairs_per_s']:.4g} pair-interactions/s, "
+        f"{ms:.3f} ms/step; adj {kt['adj_us']:.2f} us, fwd {kt['fwd_us']:.2f} us per launch; "
+        f"frac {out['roofline']['frac']}, whole evaluation {out['whole_eval_alu_frac']}")
+    del dev
+    return out
 
 
 def flow_leg(ctx, precision: str, k: int = 64, reps: int = 3):
@@ -236,12 +318,36 @@ def measured_traffic(name: str, precision: str):
         return None
 
 
+def host_cpu() -> dict:
+    """The host the oracle runs on: logical CPUs, the ones this process may
+    use, and the CPU model."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def oracle_threads() -> int:
+    """All the cores this process is given: the CPU share the job runs with
+    (OMP_NUM_THREADS when the launcher sets it), else every CPU of the
+    affinity mask."""
+    aff = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(aff, int(env))) if env.isdigit() and int(env) > 0 else aff
+
+
 def cpu_baseline(pb, target_s=12.0, budget_s=25.0):
-    """The FP64 oracle on the host's cores (up to 16 threads): repeated
-    loss+gradient evaluations of the same problem, about target_s seconds of
-    work in all (fewer Euler steps if one evaluation would exceed the budget)."""
+    """The FP64 oracle on the host's cores: repeated loss+gradient evaluations
+    of the same problem, about target_s seconds of work in all (fewer Euler
+    steps than the workload's T when one evaluation would exceed budget_s)."""
     import oracle
-    threads = min(16, len(os.sched_getaffinity(0)))
+    threads = oracle_threads()
     oracle.set_threads(threads)
     p0 = momentum(pb)
     # probe the rate on 2 steps, then size the sample
@@ -254,17 +360,20 @@ def cpu_baseline(pb, target_s=12.0, budget_s=25.0):
     for _ in range(evals):
         oracle.shoot_grad(pb.q0, p0, pb.target, pb.sigma, pb.lam, T)
     dt = time.perf_counter() - t0
-    # one thread, on a 2-step sample, for the paper's single-CPU framing
+    # one thread, for the paper's single-CPU framing: a 2-step evaluation of a
+    # seeded 4096-landmark subsample (the rate per pair does not depend on N)
+    from paper_1907_04839_amd import synth
+    sub = synth.subsample(pb, min(pb.n, 4096))
     oracle.set_threads(1)
     t1 = time.perf_counter()
-    oracle.shoot_grad(pb.q0, p0, pb.target, pb.sigma, pb.lam, 2)
-    one = 2 * 2 * pb.n ** 2 / (time.perf_counter() - t1)
+    oracle.shoot_grad(sub.q0, momentum(sub), sub.target, sub.sigma, sub.lam, 2)
+    one = 2 * 2 * sub.n ** 2 / (time.perf_counter() - t1)
     oracle.set_threads(threads)
-    return {"value": evals * 2 * T * pb.n ** 2 / dt, "unit": "pair-interactions/s",
+    return {"value": round(evals * 2 * T * pb.n ** 2 / dt, 1), "unit": "pair-interactions/s",
             "cores": threads, "kind": "oracle", "seconds": round(dt, 2),
-            "value_1_thread": round(one, 1),
-            "sample": f"{evals} FP64 loss+gradient evaluations of the same N={pb.n} problem "
-                      f"with T={T} Euler steps ({evals * 2 * T * pb.n ** 2:.3g} pairs)"}
+            "value_1_thread": round(one, 1), "host": host_cpu(),
+            "sample": f"{evals} FP64 loss+gradient evaluation(s) of the N={pb.n} workload with "
+                      f"T={T} of its {pb.T} Euler steps ({evals * 2 * T * pb.n ** 2:.3g} pairs)"}
 
 
 def full_solve(ctx, dev, pb, precision):
@@ -383,17 +492,38 @@ def serving(n_jobs: int, rate: float = 200.0):
             "batched_rounds": b["rounds"], "batched_job_evaluations": b["job_evaluations"]}
 
 
+def admission(n_jobs: int = 64, budget_mb: int = 64, rate: float = 200.0):
+    """The same stream through a server whose arena is only budget_mb: jobs wait
+    until their HBM footprint fits, so admission, not compute, limits the batch."""
+    from paper_1907_04839_amd import lddmm, serve
+    jobs, arrivals = serve.make_stream(n_jobs, rate)
+    cfg = lddmm.server_config(40, "fp32c", max_slots=32, max_n=8192)
+    fps = [lddmm.job_footprint(cfg, jb.n) for jb in jobs]
+    log(f"[bench] admission: {n_jobs} jobs through a {budget_mb} MB arena ...")
+    b = serve.run_batched(jobs, arrivals, hbm_budget_bytes=budget_mb << 20)
+    keep = ("jobs", "solves_per_s", "p50_s", "p99_s", "mean_s", "makespan_s")
+    out = {"workload": f"first {n_jobs} jobs of the serving stream, arena {budget_mb} MB",
+           "hbm_budget_bytes": budget_mb << 20, "job_footprint_bytes_max": max(fps),
+           "job_footprint_bytes_mean": round(sum(fps) / len(fps)),
+           "batched": {k: round(b[k], 4) for k in keep}, "batched_rounds": b["rounds"]}
+    log(f"[bench] admission-limited: {b['solves_per_s']:.3g} solves/s, p99 {b['p99_s']:.3f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="ellipsoid4096")
+    ap.add_argument("--workload", default="blobs65536",
+                    choices=["blobs65536", "ellipsoid4096", "sphere16384", "ellipsoid1847"])
     ap.add_argument("--precision", default="fp32c", choices=["fp32", "fp32c", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="skip the extra modes and sizes")
-    ap.add_argument("--serve-jobs", type=int, default=48,
+    ap.add_argument("--quick", action="store_true", help="only the headline workload")
+    ap.add_argument("--serve-jobs", type=int, default=512,
                     help="registrations of the seeded Poisson stream for the serving leg (0: skip)")
+    ap.add_argument("--admission-jobs", type=int, default=64,
+                    help="jobs through a 64 MB arena for the admission leg (0: skip)")
     ap.add_argument("--flow-only", action="store_true",
                     help="time only the grid deformation (lddmm_flow) and print its record")
     ap.add_argument("--rk4-only", action="store_true",
@@ -407,7 +537,6 @@ def main():
               "single MI355X); run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np  # noqa: F401
     import torch
     from paper_1907_04839_amd import lddmm
 
@@ -424,58 +553,58 @@ def main():
             print(json.dumps(rk4_leg(ctx, args.precision)), flush=True)
         return
     pb = workload(args.workload)
-    p0 = momentum(pb)
-    dev = {k: torch.from_numpy(v).cuda() for k, v in (("q0", pb.q0), ("x", pb.target), ("p0", p0))}
-    pairs_per_step = 2 * pb.T * pb.n ** 2
+    ckpt = pb.ckpt_every
 
+    extra = {}
+    try:
+        CEILINGS.update(measured_ceilings())
+        extra["measured_ceilings"] = dict(CEILINGS)
+    except (OSError, RuntimeError) as e:
+        log(f"[bench] rate probes unavailable: {e}")
     with lddmm.Context(0) as ctx:
         log(f"[bench] {pb.name} N={pb.n} T={pb.T} {args.precision}: warmup {args.warmup}, "
             f"timing {args.steps} steps")
-        dt, loss = time_steps(ctx, dev, pb, args.precision, args.steps, args.warmup)
-        value = pairs_per_step * args.steps / dt
-        log(f"[bench] {value:.4g} pair-interactions/s, {1e3 * dt / args.steps:.3f} ms/step, "
-            f"loss {loss:.6g}")
-        med, mn = step_event_times(ctx, dev, pb, args.precision, args.steps)
-        log(f"[bench] per-step events: median {med:.3f} ms, min {mn:.3f} ms")
-        kt = kernel_times(ctx, dev, pb, args.precision, args.steps)
-        roof = roofline(pb.n, kt, measured_traffic(args.workload, args.precision), args.precision)
-        log(f"[bench] kernels: fwd {kt['fwd_us']:.2f} us, adj {kt['adj_us']:.2f} us per launch; "
-            f"roofline frac {roof['frac']}")
+        head = measure(ctx, args.workload, args.precision, args.steps, args.warmup, ckpt)
         ctx.check()
-
-        extra = {}
         if not args.quick:
-            extra["solve"] = full_solve(ctx, dev, pb, args.precision)
+            # the other precision modes at the headline size
             modes = {}
             for prec in ("fp32", "fp32c", "fp64"):
-                k = max(2, args.steps // 4)
-                d, _ = time_steps(ctx, dev, pb, prec, k, 1)
-                modes[prec] = round(pairs_per_step * k / d, 1)
-                log(f"[bench] mode {prec}: {modes[prec]:.4g} pair-interactions/s")
-            extra["modes_pairs_per_s"] = modes
-            sizes = {}
-            for name, ck in (("sphere16384", 10), ("blobs65536", 0)):
-                b = workload(name)
-                bdev = {k: torch.from_numpy(v).cuda() for k, v in
-                        (("q0", b.q0), ("x", b.target), ("p0", momentum(b)))}
-                k = 3 if b.n <= 16384 else 2
-                d, _ = time_steps(ctx, bdev, b, args.precision, k, 1, ckpt_every=ck)
-                bkt = kernel_times(ctx, bdev, b, args.precision, 1, ckpt_every=ck)
-                sizes[name] = {"n": b.n, "T": b.T, "ckpt_every": ck,
-                               "pairs_per_s": round(2 * b.T * b.n ** 2 * k / d, 1),
-                               "ms_per_step": round(1e3 * d / k, 3),
-                               "roofline": roofline(b.n, bkt, precision=args.precision)}
-                log(f"[bench] {name}: {sizes[name]['pairs_per_s']:.4g} pair-interactions/s, "
-                    f"frac {sizes[name]['roofline']['frac']}")
-                del bdev
-            extra["sizes"] = sizes
+                if prec == args.precision:
+                    modes[prec] = {k: head[k] for k in ("pairs_per_s", "ms_per_step",
+                                                        "whole_eval_alu_frac", "roofline")}
+                    continue
+                k = max(2, min(args.steps, 3 if pb.n >= 65536 else 10))
+                m = measure(ctx, args.workload, prec, k, 1, ckpt, events=False)
+                modes[prec] = {k2: m[k2] for k2 in ("pairs_per_s", "ms_per_step",
+                                                     "whole_eval_alu_frac", "roofline")}
+            extra["modes"] = modes
+            # the 4096-landmark ellipsoid registration: evaluation rate, modes, full solve
+            if args.workload != "ellipsoid4096":
+                e = measure(ctx, "ellipsoid4096", args.precision, max(args.steps, 40), 5)
+                e["modes_pairs_per_s"] = {args.precision: e["pairs_per_s"]}
+                for prec in ("fp32", "fp32c", "fp64"):
+                    if prec != args.precision:
+                        e["modes_pairs_per_s"][prec] = measure(
+                            ctx, "ellipsoid4096", prec, 10, 1, events=False)["pairs_per_s"]
+                epb = workload("ellipsoid4096")
+                edev = {"q0": torch.from_numpy(epb.q0).cuda(),
+                        "x": torch.from_numpy(epb.target).cuda()}
+                e["solve"] = full_solve(ctx, edev, epb, args.precision)
+                extra["ellipsoid4096"] = e
+            if args.workload != "sphere16384":
+                extra["sphere16384"] = measure(ctx, "sphere16384", args.precision, 3, 1, 10,
+                                               events=False)
             extra["flow"] = flow_leg(ctx, args.precision)
             extra["paper_scale_solve"] = paper_scale_solve(ctx, args.precision)
             extra["planar"] = planar_leg(ctx, args.precision)
             extra["rk4"] = rk4_leg(ctx, args.precision)
 
-    if args.serve_jobs > 0 and not args.quick:
-        extra["serving"] = serving(args.serve_jobs)
+    if not args.quick:
+        if args.serve_jobs > 0:
+            extra["serving"] = serving(args.serve_jobs)
+        if args.admission_jobs > 0:
+            extra["admission"] = admission(args.admission_jobs, 64)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -485,22 +614,23 @@ def main():
 
     rec = {
         "metric": "pair-interactions/s fwd+adjoint (one loss+gradient evaluation)",
-        "value": round(value, 1),
+        "value": head["pairs_per_s"],
         "unit": "pair-interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(1e3 * dt / args.steps, 4),
-        "ms_per_step_events": {"median": round(med, 4), "min": round(mn, 4)},
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "ms_per_step_events": head["ms_per_step_events"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{pb.name}: N={pb.n} landmarks, T={pb.T} Euler steps, "
-                               f"sigma={pb.sigma:g}, lambda={pb.lam:g}",
-                   "precision": args.precision, "pairs_per_step": pairs_per_step},
-        "roofline": roof,
+        "config": {"workload": head["workload"], "precision": args.precision,
+                   "pairs_per_step": head["pairs_per_step"]},
+        "roofline": head["roofline"],
+        "whole_eval_alu_frac": head["whole_eval_alu_frac"],
+        "kernel_us": head["kernel_us"],
         "cpu_baseline": cpu,
     }
     rec.update(extra)

@@ -114,10 +114,16 @@ typedef struct {
 typedef struct lddmm_ctx lddmm_ctx;
 
 /* A context binds one GPU and owns a device workspace (trajectory, adjoint
- * state, partial sums), grown on demand and reused across calls.
- * device: HIP device ordinal.  *out receives the context.
+ * state, partial sums), grown on demand and reused across calls, plus the
+ * solver's workspace (lddmm_solve).
+ *   device           : HIP device ordinal
+ *   hbm_budget_bytes : cap on the two workspaces together, in bytes; a call
+ *                      whose workspace would exceed it fails with ENOMEM
+ *                      before enqueuing anything, and the context stays
+ *                      usable.  0: no cap (limited by the device's memory).
+ *   out              : receives the context
  * Errors: EINVAL (null out, bad device), EDEVICE. */
-lddmm_status lddmm_ctx_create(int device, lddmm_ctx** out);
+lddmm_status lddmm_ctx_create(int device, size_t hbm_budget_bytes, lddmm_ctx** out);
 
 /* Waits for the context's pending work, frees the workspace and the context.
  * NULL is accepted. */

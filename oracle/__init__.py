@@ -17,7 +17,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB selects another build of the same source (the sanitizer test's).
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -74,6 +75,8 @@ def lib():
                                    _dp, _dp, _dp, ctypes.POINTER(_Opts), ctypes.POINTER(_Result),
                                    _dp, ctypes.c_int]
         L.oracle_solve.restype = ctypes.c_int
+        L.oracle_cubic_step.argtypes = [ctypes.c_double] * 6
+        L.oracle_cubic_step.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -226,6 +229,14 @@ def shoot_grad(q0, p0, x, sigma: float, lam: float, T: int, compensated: bool = 
     if all_grads:
         out.update(grad_q0=gq, grad_x=gx)
     return out
+
+
+def cubic_step(a0: float, f0: float, d0: float, a1: float, f1: float, d1: float) -> float:
+    """The line search's interpolation step: the minimiser of the cubic through
+    (a0, f0, f'(a0) = d0) and (a1, f1, f'(a1) = d1), kept inside the middle 80 %
+    of the bracket, else the midpoint."""
+    return float(lib().oracle_cubic_step(float(a0), float(f0), float(d0), float(a1),
+                                         float(f1), float(d1)))
 
 
 @dataclass

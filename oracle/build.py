@@ -11,11 +11,18 @@ import subprocess
 _HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def build(verbose: bool = False) -> str:
+# Checks of the address and undefined-behaviour sanitizers, for the build the
+# sanitizer test loads instead of the plain one (same arithmetic flags).
+SANITIZE = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+            "-fno-omit-frame-pointer", "-g"]
+
+
+def build(verbose: bool = False, out: str | None = None, sanitize: bool = False) -> str:
     src = os.path.join(_HERE, "lddmm_oracle.c")
-    out = os.path.join(_HERE, "liboracle.so")
+    out = out or os.path.join(_HERE, "liboracle.so")
     tmp = out + ".tmp"
-    cmd = ["gcc", "-O3", "-std=c11", "-Wall", "-Wextra", "-ffp-contract=off", "-fno-fast-math",
+    cmd = ["gcc", "-O1" if sanitize else "-O3", "-std=c11", "-Wall", "-Wextra",
+           "-ffp-contract=off", "-fno-fast-math", *(SANITIZE if sanitize else []),
            "-fPIC", "-shared", "-o", tmp, src, "-lm", "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -644,6 +644,12 @@ static double cubic_step(double a0, double f0, double d0, double a1, double f1, 
     return a;
 }
 
+/* The same step, exported for the tests that pin it against closed-form
+ * minimisers of cubics and its fallback branches. */
+double oracle_cubic_step(double a0, double f0, double d0, double a1, double f1, double d1) {
+    return cubic_step(a0, f0, d0, a1, f1, d1);
+}
+
 /* Strong-Wolfe line search along d from x (f, g given), N&W Algs. 3.5/3.6.
  * On success writes the accepted point to xn, fn, gn and returns 1. */
 static int line_search(objective *o, size_t m, const double *x, double f, const double *g,

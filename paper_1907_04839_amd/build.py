@@ -10,6 +10,8 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblddmm.so")
 
 SOURCES = ["shoot_kernels.hip", "lbfgs.hip", "lddmm_api.cpp", "serve.cpp"]
+PROBE_SOURCES = ["rate_probe.hip"]
+PROBE_LIB = os.path.join(PKG, "librate_probe.so")
 
 # Packed FP32 instructions are switched off for the device code.
 HIPCC_FLAGS = [
@@ -26,16 +28,24 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
+def _hipcc(sources, out: str, verbose: bool) -> str:
+    tmp = out + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+           *[os.path.join(CSRC, s) for s in sources], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """liblddmm.so, and the issue-rate probes the benchmark loads on their own
+    (librate_probe.so)."""
+    _hipcc(SOURCES, LIB, verbose)
+    _hipcc(PROBE_SOURCES, PROBE_LIB, verbose)
     return LIB
 
 

@@ -69,6 +69,7 @@ struct Timer {
 
 struct lddmm_ctx {
   int device = 0;
+  size_t budget = 0;         // cap on ws_bytes + sws_bytes (0: none)
   void* ws = nullptr;        // workspace
   size_t ws_bytes = 0;
   int* flag = nullptr;       // device non-finite flag
@@ -153,57 +154,15 @@ lddmm_status check_params(lddmm_ctx* ctx, const lddmm_params* p) {
   return LDDMM_OK;
 }
 
-size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
-
-// Byte offsets of the workspace buffers of one problem.
-struct Layout {
-  size_t st, ad, hp0, hq0, xc, cen, h0p, out3, traj, arec, ckpt, partial;
-  size_t hpT, hqT, hTp, stT, recT;   // energy at t = 1 only (else empty)
-  size_t rk_acc, rk_lam;             // Runge-Kutta steps only (else empty)
-  size_t total;
-  int slots;   // trajectory slots (records: 1 per Euler step, 4 per Runge-Kutta step)
-  int nseg;    // checkpoint segments (0 = full trajectory)
-};
-
-Layout make_layout(const lddmm_params& p, const Plan& plan) {
-  Layout L{};
-  const size_t n = (size_t)p.n, rb = rec_bytes(p.precision), ab = acc_bytes(p.precision);
-  size_t off = 0;
-  auto take = [&](size_t bytes) { size_t o = off; off += a256(bytes); return o; };
-  L.st = take(6 * n * 8);
-  L.ad = take(6 * n * 8);
-  L.hp0 = take(3 * n * 8);
-  L.hq0 = take(3 * n * 8);
-  L.xc = take(3 * n * 8);
-  L.cen = take(4 * 8);
-  L.h0p = take((size_t)plan.nb * 8);
-  L.out3 = take(4 * 8);
-  const int s = p.ckpt_every;
-  const bool ck = s > 0 && s < p.T;
-  const int spt = p.integrator == LDDMM_RK4 ? 4 : 1;   // records per step
-  L.slots = spt * (ck ? s : p.T) + 1;
-  L.nseg = ck ? (p.T + s - 1) / s : 0;
-  L.traj = take((size_t)L.slots * n * rb);
-  L.arec = take(2 * n * rb);
-  L.ckpt = take((size_t)L.nseg * 6 * n * 8);
-  L.partial = take(plan.S > 1 ? (size_t)plan.S * 9 * n * ab : 0);
-  const bool fin = p.energy == LDDMM_ENERGY_FINAL;
-  L.hpT = take(fin ? 3 * n * 8 : 0);
-  L.hqT = take(fin ? 3 * n * 8 : 0);
-  L.hTp = take(fin ? (size_t)plan.nb * 8 : 0);
-  L.stT = take(fin ? 6 * n * 8 : 0);
-  L.recT = take(fin ? n * rb : 0);
-  L.rk_acc = take(spt == 4 ? 6 * n * 8 : 0);
-  L.rk_lam = take(spt == 4 ? 6 * n * 8 : 0);
-  L.total = off;
-  return L;
-}
-
 template <typename T>
 T* at(void* base, size_t off) { return reinterpret_cast<T*>(static_cast<char*>(base) + off); }
 
 lddmm_status ensure_ws(lddmm_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->ws_bytes) return LDDMM_OK;
+  if (ctx->budget && (bytes > ctx->budget || ctx->sws_bytes > ctx->budget - bytes))
+    return fail(ctx, LDDMM_ENOMEM,
+                "workspace of %zu bytes (+ %zu of solver workspace) exceeds the context's "
+                "budget of %zu bytes", bytes, ctx->sws_bytes, ctx->budget);
   HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
   if (ctx->ws) {
     HIP_TRY(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize");
@@ -211,7 +170,8 @@ lddmm_status ensure_ws(lddmm_ctx* ctx, size_t bytes) {
     ctx->ws = nullptr;
     ctx->ws_bytes = 0;
   }
-  const size_t want = a256(bytes + bytes / 4);   // headroom for slightly larger problems
+  // headroom for slightly larger problems, unless a budget is set
+  const size_t want = ctx->budget ? a256(bytes) : a256(bytes + bytes / 4);
   if (hipMalloc(&ctx->ws, want) != hipSuccess) {
     ctx->ws = nullptr;
     (void)hipGetLastError();
@@ -363,9 +323,12 @@ lddmm_status begin(lddmm_ctx* ctx, const lddmm_params* params, Job* job, size_t 
 }
 
 // One loss+gradient evaluation (Alg. 1 ComputeGradient) of a prepared job.
+// tm: the per-kernel timer (the context's, or one that stays off).
 lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const double* p0,
                       const double* target, double* out3, double* grad, double* q1,
-                      hipStream_t s, double* grad_q0 = nullptr, double* grad_x = nullptr) {
+                      hipStream_t s, double* grad_q0 = nullptr, double* grad_x = nullptr,
+                      Timer* tm = nullptr) {
+  if (!tm) tm = &ctx->timer;
   const lddmm_params* params = &j.p;
   const int n = params->n, T = params->T, mode = params->precision;
   HIP_TRY(ctx, launch_centroid(q0, n, j.cen, s), "centroid");
@@ -374,8 +337,7 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
   if (j.L.nseg > 0)
     HIP_TRY(ctx, hipMemcpyAsync(j.ckpt_state(0), j.st, 6 * (size_t)n * 8, hipMemcpyDeviceToDevice, s),
             "checkpoint 0");
-  HIP_TRY(ctx, run_forward(j, 0, T, true, true, s, &ctx->timer, grad_q0 != nullptr),
-          "forward step");
+  HIP_TRY(ctx, run_forward(j, 0, T, true, true, s, tm, grad_q0 != nullptr), "forward step");
   const bool fin = params->energy == LDDMM_ENERGY_FINAL;
   if (fin) {
     // Energy at t = 1 (the loss as Alg. 1 evaluates it after the forward loop): the
@@ -394,7 +356,7 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
     a.hq0 = j.hqT;
     a.h0_part = j.hTp;
     a.partial = j.partial;
-    HIP_TRY(ctx, launch_fwd_step(mode, j.plan, a, s, ctx->timer.take(0)), "final energy");
+    HIP_TRY(ctx, launch_fwd_step(mode, j.plan, a, s, tm->take(0)), "final energy");
   }
   const double rscale = j.spt == 4 ? j.sc.dt / 6.0 : 1.0;   // first stage adjoint: dt/6 lambda
   HIP_TRY(ctx, launch_loss(mode, n, j.plan.nb, params->lambda, j.sc.bscale, rscale, j.st, j.xc,
@@ -403,7 +365,7 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
           "loss");
   int cur = 0;
   if (j.L.nseg == 0) {
-    HIP_TRY(ctx, run_adjoint(j, 0, T, &cur, grad, s, &ctx->timer, grad_q0), "adjoint step");
+    HIP_TRY(ctx, run_adjoint(j, 0, T, &cur, grad, s, tm, grad_q0), "adjoint step");
   } else {
     const int every = params->ckpt_every;
     for (int seg = j.L.nseg - 1; seg >= 0; --seg) {
@@ -411,9 +373,9 @@ lddmm_status run_grad(lddmm_ctx* ctx, const Job& j, const double* q0, const doub
       if (seg != j.L.nseg - 1) {   // the last segment is still in the ring of slots
         HIP_TRY(ctx, launch_restore(mode, n, j.ckpt_state(seg), j.sc.k, j.st, j.rec(t0), s),
                 "restore");
-        HIP_TRY(ctx, run_forward(j, t0, t1, false, false, s, &ctx->timer), "recompute step");
+        HIP_TRY(ctx, run_forward(j, t0, t1, false, false, s, tm), "recompute step");
       }
-      HIP_TRY(ctx, run_adjoint(j, t0, t1, &cur, grad, s, &ctx->timer, grad_q0), "adjoint step");
+      HIP_TRY(ctx, run_adjoint(j, t0, t1, &cur, grad, s, tm, grad_q0), "adjoint step");
     }
   }
   return LDDMM_OK;
@@ -440,7 +402,7 @@ const char* lddmm_status_string(lddmm_status s) {
 
 const char* lddmm_last_error(lddmm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
 
-lddmm_status lddmm_ctx_create(int device, lddmm_ctx** out) {
+lddmm_status lddmm_ctx_create(int device, size_t hbm_budget_bytes, lddmm_ctx** out) {
   if (!out) return fail(nullptr, LDDMM_EINVAL, "out is NULL");
   *out = nullptr;
   int count = 0;
@@ -453,6 +415,7 @@ lddmm_status lddmm_ctx_create(int device, lddmm_ctx** out) {
   lddmm_ctx* c = new (std::nothrow) lddmm_ctx;
   if (!c) return fail(nullptr, LDDMM_ENOMEM, "host allocation failed");
   c->device = device;
+  c->budget = hbm_budget_bytes;
   e = hipMalloc(&c->flag, 256);
   if (e == hipSuccess) e = hipMemset(c->flag, 0, 256);
   if (e == hipSuccess) e = hipHostMalloc(&c->host_done, 2 * sizeof(int), hipHostMallocDefault);
@@ -666,6 +629,10 @@ lddmm_status lddmm_solve(lddmm_ctx* ctx, const lddmm_params* params, const lddmm
   const size_t o_res = take(sizeof(LbfgsResult));
   const size_t o_trace = take(2 * ((size_t)opts->max_iter + 1) * 8);
   if (off > ctx->sws_bytes) {
+    if (ctx->budget && (off > ctx->budget || ctx->ws_bytes > ctx->budget - off))
+      return fail(ctx, LDDMM_ENOMEM,
+                  "solver workspace of %zu bytes (+ %zu of workspace) exceeds the context's "
+                  "budget of %zu bytes", off, ctx->ws_bytes, ctx->budget);
     HIP_TRY(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize");
     if (ctx->sws) HIP_TRY(ctx, hipFree(ctx->sws), "hipFree");
     ctx->sws = nullptr;

@@ -6,46 +6,9 @@
 #include <cstddef>
 #include <cstdint>
 
+#include "plan.h"
+
 namespace lddmm {
-
-// Precision of the pair sums (the FP64 state, loss and optimiser are FP64 in
-// every mode).
-enum Mode : int { kFP32 = 0, kFP32Comp = 1, kFP64 = 2 };
-
-// Work decomposition of one N x N pair sum.  Landmark i is owned by lane
-// (i mod 64) of a wave of i-block ib = i / 64; the j range is split into S
-// chunks (one workgroup each) and, inside a workgroup, over W waves.
-// Partial sums of different chunks are combined in chunk order.
-struct Plan {
-  int n;        // landmarks
-  int nb;       // i-blocks of 64
-  int S;        // j-chunks (workgroups) per i-block
-  int W;        // waves per workgroup of the forward pair kernel
-  int chunk;    // j per workgroup
-  int wchunk;   // j per wave of the forward pair kernel
-  int Wa;       // waves per workgroup of the adjoint pair kernel
-  int wchunk_a; // j per wave of the adjoint pair kernel
-};
-
-Plan make_plan(int n, int target_waves);
-
-// The workgroup widths measured fastest for the pair kernels of a precision
-// mode and kind of step (rk: Runge-Kutta stages), applied to the plans of 8
-// waves and 8, 4, 3 or 2 j-chunks; other plans are left as they are.
-void widen_plan(Plan& p, int mode, bool rk);
-
-// Coordinates enter the pair kernels pre-scaled by k = sqrt(log2(e) / (2 sigma^2)),
-// so that the kernel value is exp2(-|k q_i - k q_j|^2).
-struct Scales {
-  double k;         // coordinate pre-scale
-  double hq;        // Hq = hq * sum g s (kq_i - kq_j)           = -(c / k)
-  double adj_a;     // A  = adj_a * (A1 / kappa - A2)            =  c / k
-  double kappa;     // 2 ln 2 = c / k^2 (independent of sigma)
-  double bscale;    // adjoint record stores b_hat = bscale * b = kappa k b
-  double dt;
-};
-
-Scales make_scales(double sigma, int T);
 
 // Arguments of one forward Euler step, or of one stage of a classical
 // Runge-Kutta step (pair sums + update).
@@ -90,10 +53,6 @@ struct AdjArgs {
   double* grad_q0;      // [n][3] dL/dq0 = a(0) + Hq(q0,p0), at t == 0 (optional)
   void* partial;        // [S][9][n] partial sums when S > 1
 };
-
-// Size in bytes of one point record and one partial-sum element.
-size_t rec_bytes(int mode);
-size_t acc_bytes(int mode);
 
 hipError_t launch_centroid(const double* q0, int n, double* cen, hipStream_t s);
 hipError_t launch_stage(int mode, int n, const double* q0, const double* p0, const double* x,

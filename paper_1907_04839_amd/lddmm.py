@@ -86,7 +86,7 @@ def lib():
             raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m "
                                "paper_1907_04839_amd.build or __graft_entry__.build())")
         L = ctypes.CDLL(LIB_PATH)
-        L.lddmm_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(_vp)]
+        L.lddmm_ctx_create.argtypes = [ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(_vp)]
         L.lddmm_ctx_destroy.argtypes = [_vp]
         L.lddmm_workspace_size.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
         L.lddmm_shoot_forward.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp]
@@ -198,12 +198,15 @@ class GradResult:
 
 
 class Context:
-    """One GPU and its reusable device workspace (``lddmm_ctx``)."""
+    """One GPU and its reusable device workspace (``lddmm_ctx``).
 
-    def __init__(self, device: int | None = None):
+    hbm_budget_bytes caps the context's workspaces (0: no cap); a call that
+    would need more raises LddmmError with status ENOMEM."""
+
+    def __init__(self, device: int | None = None, hbm_budget_bytes: int = 0):
         self.device = torch.cuda.current_device() if device is None else int(device)
         h = _vp()
-        _check(lib().lddmm_ctx_create(self.device, ctypes.byref(h)))
+        _check(lib().lddmm_ctx_create(self.device, int(hbm_budget_bytes), ctypes.byref(h)))
         self._h = h
 
     @property

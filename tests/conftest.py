@@ -51,3 +51,18 @@ def rel_err(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def row_err(a, b):
+    """Largest row error over the RMS row norm of the reference,
+    max_i |a_i - b_i| / sqrt(mean_i |b_i|^2), for [N, k] outputs.  It is never
+    smaller than rel_err, and an error confined to a few rows (one 64-landmark
+    block, a ragged tail, one j-chunk's partial) is not diluted by the others.
+    Like rel_err it never divides by a single near-zero component."""
+    import numpy as np
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    a2, b2 = a.reshape(b.shape[0], -1), b.reshape(b.shape[0], -1)
+    d = np.sqrt(((a2 - b2) ** 2).sum(axis=1)).max(initial=0.0)
+    rms = np.sqrt((b2 ** 2).sum(axis=1).mean()) if b2.size else 0.0
+    return float(d / max(rms, 1e-300))

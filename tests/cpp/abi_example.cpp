@@ -63,7 +63,7 @@ int main() {
   hipMemcpy(dx, x.data(), bytes, hipMemcpyHostToDevice);
 
   lddmm_ctx* ctx = nullptr;
-  if (lddmm_ctx_create(0, &ctx) != LDDMM_OK) {
+  if (lddmm_ctx_create(0, 0, &ctx) != LDDMM_OK) {
     std::fprintf(stderr, "ctx: %s\n", lddmm_last_error(nullptr));
     return 2;
   }

@@ -137,3 +137,4 @@ def test_size_limits_are_rejected_on_the_host(lib):
         assert L.lddmm_flow(None, P, fake, fake, m, fake, fake, None, None,
                             None) == lddmm.EINVAL
         assert b"m must be" in L.lddmm_last_error(None)
+

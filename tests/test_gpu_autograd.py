@@ -6,7 +6,7 @@ import pytest
 
 from paper_1907_04839_amd import synth
 
-from conftest import rel_err, to_dev
+from conftest import rel_err, row_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -75,7 +75,7 @@ def test_sphere_subsample_T100_matches_oracle(orc_mt, mode, tol):
     torch.cuda.synchronize()
     o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, pb.T)
     el = abs(L.item() - o["loss"]) / abs(o["loss"])
-    eg = rel_err(p0.grad.cpu().numpy(), o["grad"])
+    eg = row_err(p0.grad.cpu().numpy(), o["grad"])
     print(f"[autograd sphere512 T=100 {mode}] loss={el:.2e} grad={eg:.2e}", flush=True)
     assert el <= tol and eg <= tol
 
@@ -125,38 +125,54 @@ def test_template_and_target_gradients_through_autograd(orc_mt):
     x = to_dev(pb.target).requires_grad_(True)
     shoot_loss(p0, q0, x, pb.T, pb.sigma, pb.lam, "fp64", 0).backward()
     o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, pb.T, all_grads=True)
-    assert rel_err(p0.grad.cpu().numpy(), o["grad"]) < 1e-12
-    assert rel_err(q0.grad.cpu().numpy(), o["grad_q0"]) < 1e-12
-    assert rel_err(x.grad.cpu().numpy(), o["grad_x"]) < 1e-12
+    assert row_err(p0.grad.cpu().numpy(), o["grad"]) < 1e-12
+    assert row_err(q0.grad.cpu().numpy(), o["grad_q0"]) < 1e-12
+    assert row_err(x.grad.cpu().numpy(), o["grad_x"]) < 1e-12
     # translation identity on the device result
     tot = (q0.grad.sum(0) + x.grad.sum(0)).abs().max().item()
     assert tot < 1e-10 * q0.grad.abs().sum().item()
 
 
 def test_sphere16384_directional_derivatives_match_fp64_differences(gpu_ctx):
-    """The full 16384-landmark sphere workload (T = 100, checkpoints every 10): for
-    seeded random unit directions d, central differences of the FP64 loss (eps 1e-4)
-    agree with g . d from the FP64 gradient and, to FP32 accuracy, from the
-    compensated FP32 gradient."""
+    """The full 16384-landmark sphere workload (T = 100, checkpoints every 10): the
+    gradient from torch.autograd through the hand-written adjoint, in FP64 and in
+    compensated FP32, against central differences of the FP64 loss (eps 1e-4) in 64
+    seeded random unit directions d.  Gated normwise over the 64 directions and per
+    direction, each error over the RMS of the 64 differences."""
     import torch
+    from paper_1907_04839_amd.autograd import shoot_loss
     pb = synth.sphere_autograd()
-    q0, x, p0 = to_dev(pb.q0), to_dev(pb.target), to_dev(pb.p0)
-    ev = lambda p, mode: gpu_ctx.shoot_grad(q0, p, x, pb.T, pb.sigma, pb.lam,  # noqa: E731
-                                            precision=mode, ckpt_every=10, want_q1=False)
-    g64, g32 = ev(p0, "fp64").grad.clone(), ev(p0, "fp32c").grad.clone()
+    q0, x = to_dev(pb.q0), to_dev(pb.target)
+
+    def grad(mode):
+        p0 = to_dev(pb.p0).requires_grad_(True)
+        shoot_loss(p0, q0, x, pb.T, pb.sigma, pb.lam, mode, 10).backward()
+        return p0.grad.detach()
+    g = {"fp64": grad("fp64"), "fp32c": grad("fp32c")}
+    p0 = to_dev(pb.p0)
+    loss = lambda p: gpu_ctx.shoot_grad(q0, p, x, pb.T, pb.sigma, pb.lam,  # noqa: E731
+                                        precision="fp64", ckpt_every=10, want_q1=False).loss.item()
     rng = np.random.default_rng(1400)
     eps = 1e-4
-    worst = {"fp64": 0.0, "fp32c": 0.0}
-    for _ in range(8):
+    fd, gd = [], {m: [] for m in g}
+    for k in range(64):
         d = rng.standard_normal(pb.p0.shape)
         d = to_dev(d / np.linalg.norm(d))
-        lp = ev(p0 + eps * d, "fp64").loss.item()
-        lm = ev(p0 - eps * d, "fp64").loss.item()
-        fd = (lp - lm) / (2 * eps)
-        for mode, g in (("fp64", g64), ("fp32c", g32)):
-            gd = float((g * d).sum())
-            worst[mode] = max(worst[mode], abs(gd - fd) / abs(fd))
+        fd.append((loss(p0 + eps * d) - loss(p0 - eps * d)) / (2 * eps))
+        for m in g:
+            gd[m].append(float((g[m] * d).sum()))
+        if k % 16 == 15:
+            print(f"[sphere16384 directional FD] {k + 1} directions", flush=True)
     torch.cuda.synchronize()
-    print(f"[sphere16384 directional FD] fp64 {worst['fp64']:.2e} fp32c {worst['fp32c']:.2e}",
+    fd = np.array(fd)
+    rms = float(np.sqrt(np.mean(fd ** 2)))
+    errs = {}
+    for m in g:
+        v = np.array(gd[m])
+        errs[m] = (float(np.linalg.norm(v - fd) / np.linalg.norm(fd)),
+                   float(np.abs(v - fd).max() / rms))
+    print("[sphere16384 directional FD, 64 directions] " +
+          " ".join(f"{m}: normwise {a:.2e} worst/rms {b:.2e}" for m, (a, b) in errs.items()),
           flush=True)
-    assert worst["fp64"] < 1e-6 and worst["fp32c"] < 1e-4
+    assert max(errs["fp64"]) < 1e-6
+    assert errs["fp32c"][0] < 1e-5 and errs["fp32c"][1] < 1e-4

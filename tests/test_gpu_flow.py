@@ -8,7 +8,7 @@ import pytest
 
 from paper_1907_04839_amd import synth
 
-from conftest import rel_err, to_dev
+from conftest import row_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -33,7 +33,7 @@ def test_velocity_matches_oracle(gpu_ctx, orc_mt, mode, n, m):
     v = gpu_ctx.velocity(to_dev(pb.q0), to_dev(pb.p0), to_dev(x), pb.sigma, precision=mode)
     torch.cuda.synchronize()
     ref = orc_mt.velocity(pb.q0, pb.p0, x, pb.sigma)
-    e = rel_err(host(v), ref)
+    e = row_err(host(v), ref)
     print(f"[velocity n={n} m={m} {mode}] {e:.2e}", flush=True)
     assert e <= TOL[mode]
 
@@ -48,8 +48,8 @@ def test_flow_matches_oracle(gpu_ctx, orc_mt, mode, n, m, T):
                              precision=mode, want_landmarks=True)
     torch.cuda.synchronize()
     ref = orc_mt.flow(pb.q0, pb.p0, x0, pb.sigma, T)
-    ed = rel_err(host(x1) - x0, ref["x1"] - x0)          # error relative to the displacement
-    eq = rel_err(host(q1) - pb.q0, ref["q1"] - pb.q0)
+    ed = row_err(host(x1) - x0, ref["x1"] - x0)          # error relative to the displacement
+    eq = row_err(host(q1) - pb.q0, ref["q1"] - pb.q0)
     print(f"[flow n={n} m={m} T={T} {mode}] points={ed:.2e} landmarks={eq:.2e}", flush=True)
     assert ed <= TOL[mode] and eq <= TOL[mode]
 
@@ -104,7 +104,7 @@ def test_points_on_the_landmarks_follow_them(gpu_ctx):
     x1, q1, _ = gpu_ctx.flow(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.q0), 8, pb.sigma,
                              precision="fp64", want_landmarks=True)
     torch.cuda.synchronize()
-    assert rel_err(host(x1) - pb.q0, host(q1) - pb.q0) < 1e-13
+    assert row_err(host(x1) - pb.q0, host(q1) - pb.q0) < 1e-13
 
 
 @pytest.mark.parametrize("mode,tol", [("fp64", 1e-12), ("fp32c", 1e-5)])
@@ -120,7 +120,7 @@ def test_ellipsoid_grid64_sampled_points_match_oracle(gpu_ctx, orc_mt, mode, tol
     idx = np.sort(np.random.default_rng(980).choice(len(grid), 256, replace=False))
     idx[-1] = len(grid) - 1                                   # the ragged end of the grid
     ref = orc_mt.flow(pb.q0, pb.p0, grid[idx], pb.sigma, pb.T)["x1"]
-    e = rel_err(x1[idx] - grid[idx], ref - grid[idx])
+    e = row_err(x1[idx] - grid[idx], ref - grid[idx])
     moved = np.abs(x1 - grid).max()
     print(f"[flow ellipsoid4096 grid64 {mode}] sampled={e:.2e} max move={moved:.2f}", flush=True)
     assert e <= tol and moved > 1.0

@@ -3,13 +3,14 @@ oracle's Runge-Kutta steps and their exact stage adjoint, through the C ABI:
 forward, loss and all three gradients, both energy terms, checkpoint segments,
 the flow of points, the solver, autograd and the server's rejection.
 
-Bar as for Euler steps: 1e-12 for FP64, 1e-5 for both FP32 modes, normwise."""
+Bar as for Euler steps: 1e-12 for FP64, 1e-5 for both FP32 modes, on [N,3]
+outputs row by row (row_err)."""
 import numpy as np
 import pytest
 
 from paper_1907_04839_amd import synth
 
-from conftest import rel_err, to_dev
+from conftest import rel_err, row_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -30,7 +31,7 @@ def test_rk4_forward_matches_oracle(gpu_ctx, orc_mt, mode, n, T):
                                        precision=mode, integrator="rk4")
     torch.cuda.synchronize()
     o = orc_mt.shoot_forward(pb.q0, pb.p0, pb.sigma, T, integrator="rk4")
-    e = (rel_err(host(q1), o["q1"]), rel_err(host(p1), o["p1"]),
+    e = (row_err(host(q1), o["q1"]), row_err(host(p1), o["p1"]),
          abs(float(H0) - o["H0"]) / o["H0"])
     print(f"[rk4 fwd n={n} T={T} {mode}] q1={e[0]:.2e} p1={e[1]:.2e} H0={e[2]:.2e}", flush=True)
     assert max(e) <= TOL[mode]
@@ -51,11 +52,38 @@ def test_rk4_gradients_match_oracle(gpu_ctx, orc_mt, mode, n, T, ckpt, energy):
                           energy=energy, integrator="rk4")
     errs = dict(loss=abs(r.loss.item() - o["loss"]) / abs(o["loss"]),
                 H=abs(r.H0.item() - o["H0"]) / abs(o["H0"]),
-                q1=rel_err(host(r.q1), o["q1"]), grad=rel_err(host(r.grad), o["grad"]),
-                grad_q0=rel_err(host(r.grad_q0), o["grad_q0"]),
-                grad_x=rel_err(host(r.grad_x), o["grad_x"]))
+                q1=row_err(host(r.q1), o["q1"]), grad=row_err(host(r.grad), o["grad"]),
+                grad_q0=row_err(host(r.grad_q0), o["grad_q0"]),
+                grad_x=row_err(host(r.grad_x), o["grad_x"]))
     print(f"[rk4 grad n={n} T={T} ckpt={ckpt} {energy} {mode}] "
           + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    assert max(errs.values()) <= TOL[mode], errs
+
+
+# Runge-Kutta stage kernels take their own workgroup widths (widened only in
+# launches of at most one workgroup per CU): sizes at the ends of the (8,2)
+# plans (144, 271: not widened, fewer than 16 j per wave), the (8,3) plan at
+# 350 (FP64 16/16), the (8,4) plan at 800 (FP32-compensated 12/12, FP64 16/16),
+# and the (8,8) plan at 1847 (FP32-compensated 12/12, FP64 16/16: 232
+# workgroups) and 4096 (512 workgroups: stage kernels stay 8/8).
+RK4_PLAN_SWEEP = [144, 271, 350, 800, 1847, 4096]
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n", RK4_PLAN_SWEEP)
+def test_rk4_every_stage_plan_matches_oracle(gpu_ctx, orc_mt, mode, n):
+    import torch
+    pb = synth.random_problem(900 + n, n, T=2)
+    r = gpu_ctx.shoot_grad(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), 2, pb.sigma, pb.lam,
+                           precision=mode, want_grad_q0=True, integrator="rk4")
+    torch.cuda.synchronize()
+    o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, 2, all_grads=True,
+                          integrator="rk4")
+    errs = dict(loss=abs(r.loss.item() - o["loss"]) / abs(o["loss"]),
+                q1=row_err(host(r.q1), o["q1"]), grad=row_err(host(r.grad), o["grad"]),
+                grad_q0=row_err(host(r.grad_q0), o["grad_q0"]))
+    print(f"[rk4 plan n={n} {mode}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()),
+          flush=True)
     assert max(errs.values()) <= TOL[mode], errs
 
 
@@ -101,7 +129,7 @@ def test_rk4_flow_matches_oracle(gpu_ctx, orc_mt, mode, ckpt):
                              integrator="rk4")
     torch.cuda.synchronize()
     o = orc_mt.flow(pb.q0, pb.p0, x0, pb.sigma, pb.T, integrator="rk4")
-    e = (rel_err(host(x1), o["x1"]), rel_err(host(q1), o["q1"]))
+    e = (row_err(host(x1), o["x1"]), row_err(host(q1), o["q1"]))
     print(f"[rk4 flow ckpt={ckpt} {mode}] x1={e[0]:.2e} q1={e[1]:.2e}", flush=True)
     assert max(e) <= TOL[mode]
 
@@ -147,9 +175,9 @@ def test_rk4_autograd_matches_oracle(orc_mt):
     o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, pb.T, all_grads=True,
                           integrator="rk4")
     assert abs(L.item() - o["loss"]) <= 1e-12 * abs(o["loss"])
-    assert rel_err(host(p0.grad), o["grad"]) <= 1e-12
-    assert rel_err(host(q0.grad), o["grad_q0"]) <= 1e-12
-    assert rel_err(host(x.grad), o["grad_x"]) <= 1e-12
+    assert row_err(host(p0.grad), o["grad"]) <= 1e-12
+    assert row_err(host(q0.grad), o["grad_q0"]) <= 1e-12
+    assert row_err(host(x.grad), o["grad_x"]) <= 1e-12
 
 
 def test_euler_server_rejects_rk4_jobs():
@@ -189,7 +217,7 @@ def test_rk4_planar_equals_3d_and_oracle(gpu_ctx, orc_mt, mode):
     np.testing.assert_array_equal(host(f2), host(f3))
     o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, pb.T, all_grads=True,
                           integrator="rk4")
-    e = max(rel_err(host(r2.grad), o["grad"]), rel_err(host(r2.grad_q0), o["grad_q0"]),
+    e = max(row_err(host(r2.grad), o["grad"]), row_err(host(r2.grad_q0), o["grad_q0"]),
             abs(r2.loss.item() - o["loss"]) / abs(o["loss"]))
     print(f"[rk4 planar {mode}] vs oracle {e:.2e}", flush=True)
     assert e <= TOL[mode]

@@ -26,6 +26,14 @@ def gpu_solve(ctx, pb, mode, **opts):
     return r
 
 
+def gpu_q1(ctx, pb, p0):
+    """q(1) of a GPU solution, by the library's FP64 forward flow."""
+    import torch
+    q1, _, _ = ctx.shoot_forward(to_dev(pb.q0), to_dev(p0), pb.T, pb.sigma, precision="fp64")
+    torch.cuda.synchronize()
+    return q1.cpu().numpy()
+
+
 def test_single_landmark_closed_form(gpu_ctx):
     q0 = np.array([[1.0, 2.0, 3.0]])
     x = np.array([[4.0, 0.0, 3.5]])
@@ -84,7 +92,7 @@ def test_ellipsoid4096_solver_trace_matches_oracle(gpu_ctx, orc_mt, mode):
                      orc_mt.SolveOpts(max_iter=its, gtol=gtol))
     k = min(len(o["trace"]), len(g["trace"]))
     tr = float((np.abs(g["trace"][:k, 0] - o["trace"][:k, 0]) / np.abs(o["trace"][:k, 0])).max())
-    q1g = orc_mt.shoot_forward(pb.q0, g["p0"], pb.sigma, pb.T)["q1"]
+    q1g = gpu_q1(gpu_ctx, pb, g["p0"])
     q1o = orc_mt.shoot_forward(pb.q0, o["p0"], pb.sigma, pb.T)["q1"]
     e = dict(loss=abs(g["loss"] - o["loss"]) / o["loss"], q1=rel_err(q1g, q1o),
              p0=rel_err(g["p0"], o["p0"]), trace_loss=tr)

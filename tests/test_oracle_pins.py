@@ -732,3 +732,94 @@ def test_rk4_single_landmark_flow_converges_at_fourth_order(orc):
                          - np.array(exact)).max()) for T in (4, 8, 16)]
     assert errs[0] < 1e-3
     assert 12.0 < errs[0] / errs[1] < 20.0 and 12.0 < errs[1] / errs[2] < 20.0, errs
+
+
+# ---------------------------------------------------------------- row-subset helpers
+
+def test_forward_row_subset_equals_full_rows_bitwise(orc):
+    """pair_forward_rows (the checker of sampled rows at full size) sums each
+    listed row exactly as pair_forward does: bitwise equal, rows in any order,
+    repeated rows included."""
+    q, p, rng = rand(2201, 700)
+    Hq, Hp = orc.pair_forward(q, p, 1.3)
+    rows = np.concatenate([[0, 699, 5, 5], rng.choice(700, size=60, replace=False)])
+    Hq_r, Hp_r = orc.pair_forward_rows(q, p, 1.3, rows)
+    np.testing.assert_array_equal(Hq_r, Hq[rows])
+    np.testing.assert_array_equal(Hp_r, Hp[rows])
+
+
+def test_adjoint_row_subset_equals_full_rows_bitwise(orc):
+    """pair_adjoint_rows sums each listed row exactly as pair_adjoint does."""
+    q, p, rng = rand(2202, 650)
+    a, b = rng.standard_normal((650, 3)), 0.3 * rng.standard_normal((650, 3))
+    A, B = orc.pair_adjoint(q, p, a, b, 1.1)
+    rows = np.concatenate([[649, 0, 17, 17], rng.choice(650, size=50, replace=False)])
+    A_r, B_r = orc.pair_adjoint_rows(q, p, a, b, 1.1, rows)
+    np.testing.assert_array_equal(A_r, A[rows])
+    np.testing.assert_array_equal(B_r, B[rows])
+
+
+# ---------------------------------------------------------------- line-search interpolation
+
+def _cubic(c):
+    """phi(a) = c0 + c1 a + c2 a^2 + c3 a^3 and its derivative."""
+    f = lambda a: c[0] + c[1] * a + c[2] * a * a + c[3] * a ** 3  # noqa: E731
+    d = lambda a: c[1] + 2 * c[2] * a + 3 * c[3] * a * a  # noqa: E731
+    return f, d
+
+
+def _step(orc, f, d, a0, a1):
+    return orc.cubic_step(a0, f(a0), d(a0), a1, f(a1), d(a1))
+
+
+def test_cubic_step_finds_the_minimiser_of_a_cubic(orc):
+    """The step interpolates a cubic from two values and two slopes, so on a
+    cubic it returns that cubic's local minimiser exactly (Nocedal & Wright,
+    eq. 3.59): phi'(a) = 3 (a - r1)(a - r2) has its minimum at the larger root;
+    the bracket's ends may come in either order."""
+    for r1, r2, a0, a1 in [(0.3, 0.62, 0.0, 1.0), (-4.0, 2.5, 1.0, 3.0), (0.1, 0.45, 0.7, 0.2),
+                           (-1.0, 1e-3, -0.0005, 0.004)]:
+        c = (0.7, 3 * r1 * r2, -1.5 * (r1 + r2), 1.0)   # phi' = 3 a^2 - 3 (r1 + r2) a + 3 r1 r2
+        f, d = _cubic(c)
+        for x0, x1 in ((a0, a1), (a1, a0)):
+            got = _step(orc, f, d, x0, x1)
+            assert abs(got - r2) <= 1e-12 * max(1.0, abs(r2)), (r1, r2, x0, x1, got)
+
+
+def test_cubic_step_on_a_quadratic_and_random_cubics(orc):
+    """A quadratic is its own interpolating cubic: the step lands on its vertex.
+    Random cubics with a local minimum inside the middle of the bracket: the
+    step equals the minimiser that numpy's polynomial roots give."""
+    f = lambda a: 2.0 * (a - 0.4) ** 2 - 1.0  # noqa: E731
+    d = lambda a: 4.0 * (a - 0.4)  # noqa: E731
+    assert abs(_step(orc, f, d, 0.0, 1.0) - 0.4) < 1e-14
+    rng = np.random.default_rng(2203)
+    checked = 0
+    while checked < 200:
+        c = rng.standard_normal(4)
+        a0, a1 = np.sort(rng.uniform(-3, 3, size=2))
+        roots = np.roots([3 * c[3], 2 * c[2], c[1]])
+        mins = [r.real for r in roots if abs(r.imag) < 1e-12 and 2 * c[2] + 6 * c[3] * r.real > 0]
+        w = a1 - a0
+        if len(mins) != 1 or not (a0 + 0.15 * w < mins[0] < a1 - 0.15 * w):
+            continue
+        fc, dc = _cubic(c)
+        got = _step(orc, fc, dc, a0, a1)
+        assert abs(got - mins[0]) <= 1e-9 * max(1.0, abs(mins[0])), (c, a0, a1, got, mins[0])
+        checked += 1
+
+
+def test_cubic_step_falls_back_to_the_midpoint(orc):
+    """No usable minimiser gives the bracket's midpoint: a cubic without a local
+    minimum (phi' = 3 a^2 + 1 > 0: the discriminant of eq. 3.59 is negative), a
+    minimiser outside the middle 80 % of the bracket (at 0.95 and at 0.05 of
+    [0, 1]), and non-finite data."""
+    f, d = _cubic((0.0, 1.0, 0.0, 1.0))
+    assert _step(orc, f, d, 0.0, 1.0) == 0.5
+    for r2 in (0.95, 0.05):
+        r1 = r2 - 2.0
+        f, d = _cubic((0.0, 3 * r1 * r2, -1.5 * (r1 + r2), 1.0))
+        assert _step(orc, f, d, 0.0, 1.0) == 0.5
+        assert _step(orc, f, d, 1.0, 0.0) == 0.5
+    assert orc.cubic_step(0.0, 0.0, -1.0, 2.0, float("inf"), 1.0) == 1.0
+    assert orc.cubic_step(0.0, 0.0, -1.0, 2.0, 1.0, float("nan")) == 1.0
