@@ -40,6 +40,19 @@ def orc_mt(orc):
     return orc
 
 
+# Per-row gates (row_err) of the workload-size tests in the FP32 modes.  The
+# contract is normwise (rel_err <= 1e-5 in FP32, 1e-12 in FP64); the row gate
+# localises errors on top of it.  FP32 rows carry the rounding of the FP32
+# positions in every pair term (an error of about one ulp of |k q| in each
+# difference k q_i - k q_j, not reduced by compensated sums), which the
+# backward pass carries through T steps: on the 4096-landmark ellipsoid at
+# T = 40 every i-block's largest row error is 0.6-3e-5 (FP32-compensated)
+# against 3-5e-6 normwise, in both the 8- and the 12-wave plans and on the
+# same rows, so the FP32 row gate sits at 10x the normwise one.  FP64 rows
+# keep the normwise bar.
+ROW_TOL = {"fp64": 1e-12, "fp32c": 1e-4, "fp32": 1e-4}
+
+
 def to_dev(a):
     import numpy as np
     import torch
@@ -54,15 +67,34 @@ def rel_err(a, b):
 
 
 def row_err(a, b):
-    """Largest row error over the RMS row norm of the reference,
-    max_i |a_i - b_i| / sqrt(mean_i |b_i|^2), for [N, k] outputs.  It is never
-    smaller than rel_err, and an error confined to a few rows (one 64-landmark
-    block, a ragged tail, one j-chunk's partial) is not diluted by the others.
-    Like rel_err it never divides by a single near-zero component."""
+    """Largest row error, each row's error taken relative to that row's own
+    norm floored at the RMS row norm of the reference:
+    max_i |a_i - b_i| / max(|b_i|, sqrt(mean_i |b_i|^2)), for [N, k] outputs.
+    An error confined to a few rows (one 64-landmark block, a ragged tail, one
+    j-chunk's partial) shows at its own relative size instead of being diluted
+    by the other rows, as it is in rel_err; a row far larger than the typical
+    one is held to its own relative error, and near-zero rows (or components)
+    to the typical row's scale, so nothing divides by a near-zero value."""
     import numpy as np
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     a2, b2 = a.reshape(b.shape[0], -1), b.reshape(b.shape[0], -1)
-    d = np.sqrt(((a2 - b2) ** 2).sum(axis=1)).max(initial=0.0)
-    rms = np.sqrt((b2 ** 2).sum(axis=1).mean()) if b2.size else 0.0
-    return float(d / max(rms, 1e-300))
+    if not b2.size:
+        return 0.0
+    d = np.sqrt(((a2 - b2) ** 2).sum(axis=1))
+    rms = np.sqrt((b2 ** 2).sum(axis=1).mean())
+    scale = np.maximum(np.sqrt((b2 ** 2).sum(axis=1)), max(rms, 1e-300))
+    return float((d / scale).max(initial=0.0))
+
+
+def point_errs(name, a, b):
+    """{name: normwise error, name_row: per-row error} of an [N, k] output."""
+    return {name: rel_err(a, b), name + "_row": row_err(a, b)}
+
+
+def assert_gates(errs, mode, tol):
+    """Every error within its gate: keys ending in "_row" at ROW_TOL[mode] in
+    the FP32 modes (tol in FP64), every other key at tol."""
+    for k, v in errs.items():
+        bar = ROW_TOL[mode] if (k.endswith("_row") and mode != "fp64") else tol
+        assert v <= bar, (k, v, bar, errs)

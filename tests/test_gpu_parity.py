@@ -1,8 +1,11 @@
 """GPU path vs the FP64 CPU oracle, through the C ABI.
 
 Bar: 1e-12 for the FP64 path and 1e-5 for both FP32 paths, on scalars as
-|diff|/|ref| and on [N,3] outputs row by row, max_i |x_i - ref_i| over the RMS
-row norm of the reference (row_err), which also bounds the normwise error.  Sizes span several
+|diff|/|ref| and on [N,3] outputs normwise (rel_err) and row by row (row_err:
+each row's error over its own norm, floored at the RMS row norm).  The
+multi-step gradients of the full-size workloads (check_grad) hold their FP32
+rows to ROW_TOL (10x, the rounding of FP32 positions carried through T
+steps); every other row gate here is at the normwise bar.  Sizes span several
 64-wide i-blocks, j-splits over several workgroups and ragged tails; the
 full-size workloads are checked on sampled rows and through properties that
 hold at any size.
@@ -12,7 +15,7 @@ import pytest
 
 from paper_1907_04839_amd import synth
 
-from conftest import rel_err, row_err, to_dev
+from conftest import ROW_TOL, rel_err, row_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +47,7 @@ def check_grad(g, o, mode, tag=""):
         if k == "H0" and o["H0"] == 0.0:
             assert g["H0"] == 0.0
             continue
-        assert v <= TOL[mode], (k, v)
+        assert v <= (ROW_TOL if k.endswith("_row") else TOL)[mode], (k, v)
 
 
 # ----------------------------------------------------------------- forward

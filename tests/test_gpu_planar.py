@@ -7,7 +7,7 @@ import pytest
 
 from paper_1907_04839_amd import synth
 
-from conftest import rel_err, row_err, to_dev
+from conftest import assert_gates, point_errs, rel_err, row_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -34,10 +34,12 @@ def test_planar_gradients_equal_3d_and_oracle(gpu_ctx, orc_mt, mode, n, T, ckpt)
         np.testing.assert_array_equal(host(getattr(r2, k)), host(getattr(r3, k)), err_msg=k)
     assert r2.loss.item() == r3.loss.item() and r2.H0.item() == r3.H0.item()
     o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, T, all_grads=True)
-    e = max(row_err(host(r2.grad), o["grad"]), row_err(host(r2.grad_q0), o["grad_q0"]),
-            abs(r2.loss.item() - o["loss"]) / abs(o["loss"]))
-    print(f"[planar n={n} T={T} ckpt={ckpt} {mode}] vs oracle {e:.2e}", flush=True)
-    assert e <= TOL[mode]
+    e = dict(loss=abs(r2.loss.item() - o["loss"]) / abs(o["loss"]),
+             **point_errs("grad", host(r2.grad), o["grad"]),
+             **point_errs("grad_q0", host(r2.grad_q0), o["grad_q0"]))
+    print(f"[planar n={n} T={T} ckpt={ckpt} {mode}] vs oracle " +
+          " ".join(f"{k}={v:.2e}" for k, v in e.items()), flush=True)
+    assert_gates(e, mode, TOL[mode])
     for k in ("grad", "grad_q0", "q1"):
         assert not host(getattr(r2, k))[:, 2].any(), k
 

@@ -4,13 +4,14 @@ forward, loss and all three gradients, both energy terms, checkpoint segments,
 the flow of points, the solver, autograd and the server's rejection.
 
 Bar as for Euler steps: 1e-12 for FP64, 1e-5 for both FP32 modes, on [N,3]
-outputs row by row (row_err)."""
+outputs normwise and row by row (row_err; the gradients' FP32 rows at the
+row gate ROW_TOL)."""
 import numpy as np
 import pytest
 
 from paper_1907_04839_amd import synth
 
-from conftest import rel_err, row_err, to_dev
+from conftest import assert_gates, point_errs, rel_err, row_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -52,12 +53,13 @@ def test_rk4_gradients_match_oracle(gpu_ctx, orc_mt, mode, n, T, ckpt, energy):
                           energy=energy, integrator="rk4")
     errs = dict(loss=abs(r.loss.item() - o["loss"]) / abs(o["loss"]),
                 H=abs(r.H0.item() - o["H0"]) / abs(o["H0"]),
-                q1=row_err(host(r.q1), o["q1"]), grad=row_err(host(r.grad), o["grad"]),
-                grad_q0=row_err(host(r.grad_q0), o["grad_q0"]),
-                grad_x=row_err(host(r.grad_x), o["grad_x"]))
+                **point_errs("q1", host(r.q1), o["q1"]),
+                **point_errs("grad", host(r.grad), o["grad"]),
+                **point_errs("grad_q0", host(r.grad_q0), o["grad_q0"]),
+                **point_errs("grad_x", host(r.grad_x), o["grad_x"]))
     print(f"[rk4 grad n={n} T={T} ckpt={ckpt} {energy} {mode}] "
           + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
-    assert max(errs.values()) <= TOL[mode], errs
+    assert_gates(errs, mode, TOL[mode])
 
 
 # Runge-Kutta stage kernels take their own workgroup widths (widened only in
@@ -80,11 +82,12 @@ def test_rk4_every_stage_plan_matches_oracle(gpu_ctx, orc_mt, mode, n):
     o = orc_mt.shoot_grad(pb.q0, pb.p0, pb.target, pb.sigma, pb.lam, 2, all_grads=True,
                           integrator="rk4")
     errs = dict(loss=abs(r.loss.item() - o["loss"]) / abs(o["loss"]),
-                q1=row_err(host(r.q1), o["q1"]), grad=row_err(host(r.grad), o["grad"]),
-                grad_q0=row_err(host(r.grad_q0), o["grad_q0"]))
+                **point_errs("q1", host(r.q1), o["q1"]),
+                **point_errs("grad", host(r.grad), o["grad"]),
+                **point_errs("grad_q0", host(r.grad_q0), o["grad_q0"]))
     print(f"[rk4 plan n={n} {mode}] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()),
           flush=True)
-    assert max(errs.values()) <= TOL[mode], errs
+    assert_gates(errs, mode, TOL[mode])
 
 
 @pytest.mark.parametrize("mode", MODES)

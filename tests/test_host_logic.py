@@ -75,3 +75,27 @@ def test_fp64_exp2_table_matches_its_generator_and_is_accurate():
         exact = (Decimal(f) * ln2).exp()
         worst = max(worst, float(abs((Decimal(p) - exact) / exact)))
     assert worst < 2.3e-16, worst
+
+
+def test_row_gate_catches_a_block_error_that_the_normwise_gate_dilutes():
+    """The per-row gate of the parity tests: one wrong 64-landmark block (6e-5
+    relative error in its rows) at N = 3001 passes the 1e-5 normwise gate but
+    not the per-row one; a uniform 3e-6 relative error on rows whose norms
+    span two orders of magnitude passes both; a zero row is judged at the
+    typical row's scale."""
+    import numpy as np
+    from conftest import rel_err, row_err
+    rng = np.random.default_rng(5)
+    n = 3001
+    ref = rng.standard_normal((n, 3)) * np.exp(rng.uniform(-2.3, 2.3, (n, 1)))
+    blk = ref.copy()
+    blk[1024:1088] *= 1 + 6e-5
+    assert rel_err(blk, ref) < 1e-5 < row_err(blk, ref)
+    uni = ref * (1 + 3e-6 * rng.choice([-1.0, 1.0], (n, 1)))
+    assert row_err(uni, ref) < 1e-5 and rel_err(uni, ref) < 1e-5
+    ref0 = ref.copy()
+    ref0[7] = 0.0
+    off = ref0.copy()
+    off[7] = 1e-7 * np.sqrt((ref ** 2).sum(axis=1).mean())
+    assert row_err(off, ref0) < 2e-7
+    assert row_err(ref, ref) == 0.0
