@@ -469,6 +469,55 @@ def paper_scale_solve(ctx, precision):
     return out
 
 
+def alg3_leg(ctx, n: int, reps: int = 10):
+    """Sec. 2.4's materialised-matrix forward step (Alg. 3: six N x N FP32 term
+    matrices, rows summed by rocBLAS sgemv) beside liblddmm's fused forward step,
+    on the same landmarks and momentum (the ellipsoid recipe at N landmarks).
+    Context for the paper's 25-30x (Alg. 3) vs 60-70x (shared memory) framing."""
+    import torch
+    from paper_1907_04839_amd import alg3, synth
+    pb = synth.ellipsoid_warp(n=n, T=40, iters=1)
+    q0 = torch.from_numpy(pb.q0).cuda()
+    p0 = torch.from_numpy(momentum(pb)).cuda()
+    wsb = alg3.workspace_bytes(n)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    with alg3.Alg3(0) as a3:
+        out = (torch.empty_like(q0), torch.empty_like(q0))
+        mat = timed(lambda: a3.pair_forward(q0, p0, pb.sigma, ws=ws, out=out))
+        mat_alloc = timed(lambda: a3.pair_forward(q0, p0, pb.sigma, out=out))
+    fused_T = timed(lambda: ctx.shoot_forward(q0, p0, pb.T, pb.sigma, precision="fp32c"))
+    ctx.timing(reset=True)
+    ctx.set_timing(True)
+    try:
+        ctx.shoot_forward(q0, p0, pb.T, pb.sigma, precision="fp32c")
+    finally:
+        ctx.set_timing(False)
+    t = ctx.timing(reset=True)
+    fused_us = 1e3 * t["fwd_ms"] / max(t["fwd_launches"], 1)
+    del ws
+    out = {"workload": f"{pb.name}: one forward step, N={n}",
+           "materialised_ms": round(mat, 4), "materialised_with_alloc_ms": round(mat_alloc, 4),
+           "fused_step_ms": round(fused_T / pb.T, 4), "fused_pair_kernel_us": round(fused_us, 2),
+           "materialised_over_fused": round(mat / (fused_T / pb.T), 2),
+           "materialised_workspace_bytes": wsb}
+    log(f"[bench] alg3 N={n}: materialised {mat:.3f} ms ({mat_alloc:.3f} with alloc/free), fused "
+        f"{fused_T / pb.T:.4f} ms per step ({out['materialised_over_fused']}x), "
+        f"{wsb / 2**20:.0f} MiB of term matrices")
+    return out
+
+
 def serving(n_jobs: int, rate: float = 200.0):
     """Registrations of uneven N (log-uniform in [500, 8000], T 40, 100
     L-BFGS iterations, FP32 sums) arriving as Poisson(rate): continuous
@@ -528,6 +577,8 @@ def main():
                     help="time only the grid deformation (lddmm_flow) and print its record")
     ap.add_argument("--rk4-only", action="store_true",
                     help="time only the Runge-Kutta leg and print its record")
+    ap.add_argument("--alg3-only", action="store_true",
+                    help="time only the materialised-matrix (Alg. 3) ablation and print it")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="for rocprofv3 --pmc passes: a 256 MiB copy (calibration) and 2 steps")
     args = ap.parse_args()
@@ -551,6 +602,10 @@ def main():
     if args.rk4_only:
         with lddmm.Context(0) as ctx:
             print(json.dumps(rk4_leg(ctx, args.precision)), flush=True)
+        return
+    if args.alg3_only:
+        with lddmm.Context(0) as ctx:
+            print(json.dumps({f"n{n}": alg3_leg(ctx, n) for n in (1847, 4096)}), flush=True)
         return
     pb = workload(args.workload)
     ckpt = pb.ckpt_every
@@ -599,6 +654,7 @@ def main():
             extra["paper_scale_solve"] = paper_scale_solve(ctx, args.precision)
             extra["planar"] = planar_leg(ctx, args.precision)
             extra["rk4"] = rk4_leg(ctx, args.precision)
+            extra["alg3_ablation"] = {f"n{n}": alg3_leg(ctx, n) for n in (1847, 4096)}
 
     if not args.quick:
         if args.serve_jobs > 0:

@@ -12,6 +12,10 @@ LIB = os.path.join(PKG, "liblddmm.so")
 SOURCES = ["shoot_kernels.hip", "lbfgs.hip", "lddmm_api.cpp", "serve.cpp"]
 PROBE_SOURCES = ["rate_probe.hip"]
 PROBE_LIB = os.path.join(PKG, "librate_probe.so")
+# The materialised-matrix forward step (Alg. 3 ablation), linked to rocBLAS.
+ALG3_SOURCES = ["alg3_ablation.hip"]
+ALG3_LIB = os.path.join(PKG, "liblddmm_alg3.so")
+ALG3_LINK = ["-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 
 # Packed FP32 instructions are switched off for the device code.
 HIPCC_FLAGS = [
@@ -28,10 +32,10 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def _hipcc(sources, out: str, verbose: bool) -> str:
+def _hipcc(sources, out: str, verbose: bool, link=()) -> str:
     tmp = out + ".tmp"
     cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in sources], "-o", tmp]
+           *[os.path.join(CSRC, s) for s in sources], *link, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -42,10 +46,11 @@ def _hipcc(sources, out: str, verbose: bool) -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """liblddmm.so, and the issue-rate probes the benchmark loads on their own
-    (librate_probe.so)."""
+    """liblddmm.so, the issue-rate probes the benchmark loads on their own
+    (librate_probe.so) and the Alg. 3 ablation (liblddmm_alg3.so)."""
     _hipcc(SOURCES, LIB, verbose)
     _hipcc(PROBE_SOURCES, PROBE_LIB, verbose)
+    _hipcc(ALG3_SOURCES, ALG3_LIB, verbose, ALG3_LINK)
     return LIB
 
 
