@@ -29,8 +29,6 @@ struct Plan {
   int wchunk;   // j per wave of the forward pair kernel
   int Wa;       // waves per workgroup of the adjoint pair kernel
   int wchunk_a; // j per wave of the adjoint pair kernel
-  int rpl;      // landmarks per lane of the pair kernels (1, 2 or 4)
-  int ng;       // i-groups of rpl i-blocks: a launch has ng * S workgroups
 };
 
 // Coordinates enter the pair kernels pre-scaled by k = sqrt(log2(e) / (2 sigma^2)),
@@ -44,30 +42,17 @@ struct Scales {
   double dt;
 };
 
-// Landmarks per lane of the pair kernels: 1, or LDDMM_ROWS_PER_LANE (2 or 4)
-// for tuning runs.
-inline int rows_per_lane() {
-  static const int v = [] {
-    const char* e = std::getenv("LDDMM_ROWS_PER_LANE");
-    const int r = e ? std::atoi(e) : 1;
-    return (r == 2 || r == 4) ? r : 1;
-  }();
-  return v;
-}
-
 inline Plan make_plan(int n, int target_waves) {
   Plan p{};
   p.n = n;
   p.nb = (n + 63) / 64;
-  p.rpl = rows_per_lane();
-  p.ng = (p.nb + p.rpl - 1) / p.rpl;
   // Waves per i-block: enough to give the chip ~target_waves waves, at most
   // 64 and at least 16 pairs per wave.  Workgroups of at most 8 waves:
   // measured on N = 4096, 16384 and 65536, 8-wave workgroups with up to 4x
   // more waves beat 16-wave ones by 3 %, 22 % and 17 % (shorter LDS combine
   // and barriers, two workgroups per CU interleaving their phases); 64 waves
   // per i-block was the best split at N = 4096 and 16384.
-  int per_i = (target_waves + p.ng - 1) / p.ng;
+  int per_i = (target_waves + p.nb - 1) / p.nb;
   if (per_i > 64) per_i = 64;
   const int max_per_i = n / 16 > 1 ? n / 16 : 1;
   if (per_i > max_per_i) per_i = max_per_i;
@@ -130,7 +115,7 @@ inline Plan make_plan(int n, int target_waves) {
 // waves and 8, 4, 3 or 2 j-chunks; other plans are left as they are.
 inline void widen_plan(Plan& p, int mode, bool rk) {
   constexpr int kCUs = 256;   // MI355X
-  if (p.W != 8 || p.rpl != 1) return;
+  if (p.W != 8) return;
   if (p.S != 8 && p.S != 4 && p.S != 3 && p.S != 2) return;
   // make_plan also gives 8 x 2 plans at N = 144-271, where 12 or 16 waves
   // would leave fewer than 8 (or no) j per wave: the 8 x 2 widths were

@@ -24,7 +24,6 @@ bool width_ok(int w) { return w == 1 || w == 2 || w == 4 || w == 8 || w == 12 ||
 // with none empty; the waves' ranges cover every chunk; grids fit int.
 void check_plan(const lddmm::Plan& p, int n) {
   CHECK(p.n == n && p.nb == (n + 63) / 64, n);
-  CHECK(p.rpl == 1 && p.ng == p.nb, n);
   CHECK(p.S >= 1 && width_ok(p.W) && width_ok(p.Wa), n);
   CHECK((long long)p.S * p.chunk >= n && (long long)(p.S - 1) * p.chunk < n, n);
   CHECK((long long)p.W * p.wchunk >= p.chunk && (long long)p.Wa * p.wchunk_a >= p.chunk, n);

@@ -17,8 +17,7 @@ def test_plans_and_layouts_under_sanitizers(tmp_path):
                     "-I", os.path.join(ROOT, "paper_1907_04839_amd", "csrc"),
                     os.path.join(ROOT, "tests", "cpp", "plan_test.cpp"), "-o", str(exe)],
                    check=True)
-    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300,
-                         env={**os.environ, "LDDMM_ROWS_PER_LANE": ""})
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stdout + out.stderr
     assert "plans ok" in out.stdout
 
