@@ -154,6 +154,30 @@ lddmm_status lddmm_shoot_grad(lddmm_ctx* ctx, const lddmm_params* params, const 
                               const double* p0, const double* target, double* out3,
                               double* grad, double* q1, void* stream);
 
+/* lddmm_shoot_grad for callers that cannot allocate device memory (code
+ * under hipGraph stream capture, tight serving loops, hosts that forbid
+ * hipMalloc): the same arguments, kernels and results (bitwise), but the
+ * workspace is a fixed device array of 64 MiB that the library holds on every
+ * GPU it runs on until the process ends, instead of the context's growable
+ * workspace.  The call allocates nothing (no hipMalloc, hipFree or event
+ * creation) and is not timed by lddmm_ctx_set_timing.
+ *   limit : the workspace lddmm_workspace_size reports for *params must be
+ *           at most 64 MiB (e.g. n = 4096 with T = 40 in FP32-compensated
+ *           mode takes 8.3 MiB; n = 16384, T = 100 takes 63 MiB with the
+ *           whole trajectory and 26 MiB with ckpt_every = 10); larger
+ *           problems fail with ENOMEM before anything is enqueued.  The
+ *           context's hbm_budget_bytes does not apply (nothing is allocated).
+ *   sharing: every call on one GPU, from any context, uses that GPU's one
+ *           array; nothing in it needs to start at zero, and each call
+ *           writes every part it reads.  Calls whose work overlaps on one GPU
+ *           (two streams, two threads, two contexts) race and give undefined
+ *           results: serialise them.
+ * Errors: EINVAL (as lddmm_shoot_grad; ctx must not be NULL), ENOMEM (limit),
+ * EDEVICE. */
+lddmm_status lddmm_shoot_grad_noalloc(lddmm_ctx* ctx, const lddmm_params* params,
+                                      const double* q0, const double* p0, const double* target,
+                                      double* out3, double* grad, double* q1, void* stream);
+
 /* Options of lddmm_solve (L-BFGS over p0 with a strong-Wolfe line search;
  * Nocedal & Wright, Numerical Optimization, Algs. 3.5, 3.6 and 7.4). */
 typedef struct {

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblddmm.so")
 
-SOURCES = ["shoot_kernels.hip", "lbfgs.hip", "lddmm_api.cpp", "serve.cpp"]
+SOURCES = ["shoot_kernels.hip", "lbfgs.hip", "scratch.hip", "lddmm_api.cpp", "serve.cpp"]
 PROBE_SOURCES = ["rate_probe.hip"]
 PROBE_LIB = os.path.join(PKG, "librate_probe.so")
 # The materialised-matrix forward step (Alg. 3 ablation), linked to rocBLAS.

@@ -78,6 +78,7 @@ struct lddmm_ctx {
   size_t sws_bytes = 0;
   int* host_done = nullptr;  // pinned: two done flags of the solver poll
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
+  void* scratch = nullptr;   // the device's fixed scratch (lddmm_shoot_grad_noalloc)
   std::string err;
 };
 
@@ -421,6 +422,7 @@ lddmm_status lddmm_ctx_create(int device, size_t hbm_budget_bytes, lddmm_ctx** o
   if (e == hipSuccess) e = hipHostMalloc(&c->host_done, 2 * sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->poll_ev[0], hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&c->poll_ev[1], hipEventDisableTiming);
+  if (e == hipSuccess) e = scratch_address(device, &c->scratch);
   if (e != hipSuccess) {
     lddmm_ctx_destroy(c);
     return hip_fail(nullptr, e, "context allocation");
@@ -478,6 +480,28 @@ lddmm_status lddmm_shoot_grad(lddmm_ctx* ctx, const lddmm_params* params, const 
   lddmm_status st = begin(ctx, params, &j);
   if (st != LDDMM_OK) return st;
   return run_grad(ctx, j, q0, p0, target, out3, grad, q1, static_cast<hipStream_t>(stream));
+}
+
+lddmm_status lddmm_shoot_grad_noalloc(lddmm_ctx* ctx, const lddmm_params* params,
+                                      const double* q0, const double* p0, const double* target,
+                                      double* out3, double* grad, double* q1, void* stream) {
+  if (!ctx) return fail(nullptr, LDDMM_EINVAL, "ctx is NULL");
+  if (!q0 || !p0 || !target || !out3 || !grad)
+    return fail(ctx, LDDMM_EINVAL, "q0, p0, target, out3 and grad must not be NULL");
+  lddmm_status st = check_params(ctx, params);
+  if (st != LDDMM_OK) return st;
+  const Layout L = make_layout(*params, make_plan(params->n, target_waves()));
+  if (L.total > kScratchBytes)
+    return fail(ctx, LDDMM_ENOMEM,
+                "workspace of %zu bytes exceeds the fixed scratch of %zu bytes of "
+                "lddmm_shoot_grad_noalloc (use lddmm_shoot_grad, or checkpoints)",
+                L.total, kScratchBytes);
+  if (!ctx->scratch) return fail(ctx, LDDMM_EDEVICE, "no scratch address for the device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  const Job j = make_job(*params, ctx->scratch);
+  Timer off;   // timing stays off: no events are created on this path
+  return run_grad(ctx, j, q0, p0, target, out3, grad, q1, static_cast<hipStream_t>(stream),
+                  nullptr, nullptr, &off);
 }
 
 lddmm_status lddmm_shoot_grad_all(lddmm_ctx* ctx, const lddmm_params* params, const double* q0,

@@ -54,6 +54,12 @@ struct AdjArgs {
   void* partial;        // [S][9][n] partial sums when S > 1
 };
 
+// Size of the fixed device scratch of lddmm_shoot_grad_noalloc, and its device
+// address on `device` (looked up on the first call for that device, with the
+// device current; the same address afterwards).
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_address(int device, void** out);
+
 hipError_t launch_centroid(const double* q0, int n, double* cen, hipStream_t s);
 hipError_t launch_stage(int mode, int n, const double* q0, const double* p0, const double* x,
                         const double* cen, double k, double* st, double* xc, void* rec0,

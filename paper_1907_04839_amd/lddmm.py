@@ -91,6 +91,8 @@ def lib():
         L.lddmm_workspace_size.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
         L.lddmm_shoot_forward.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp]
         L.lddmm_shoot_grad.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+        L.lddmm_shoot_grad_noalloc.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp,
+                                               _vp, _vp, _vp]
         L.lddmm_shoot_grad_all.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, _vp, _vp, _vp, _vp,
                                            _vp, _vp, _vp]
         L.lddmm_velocity.argtypes = [_vp, ctypes.POINTER(Params), _vp, _vp, ctypes.c_int32, _vp,
@@ -121,7 +123,8 @@ def lib():
         L.lddmm_last_error.restype = ctypes.c_char_p
         L.lddmm_version.restype = ctypes.c_char_p
         for f in ("lddmm_ctx_create", "lddmm_ctx_destroy", "lddmm_workspace_size",
-                  "lddmm_shoot_forward", "lddmm_shoot_grad", "lddmm_shoot_grad_all",
+                  "lddmm_shoot_forward", "lddmm_shoot_grad", "lddmm_shoot_grad_noalloc",
+                  "lddmm_shoot_grad_all",
                   "lddmm_velocity", "lddmm_flow",
                   "lddmm_ctx_check",
                   "lddmm_ctx_set_timing", "lddmm_ctx_timing", "lddmm_solve_opts_default",
@@ -320,6 +323,23 @@ class Context:
                                       q1.data_ptr() if q1 is not None else None,
                                       _stream(stream)), self._h)
         return GradResult(out3[0], out3[1], out3[2], grad, q1)
+
+    def shoot_grad_noalloc(self, q0: torch.Tensor, p0: torch.Tensor, target: torch.Tensor,
+                           T: int, sigma: float, lam: float, grad: torch.Tensor,
+                           out3: torch.Tensor, q1: torch.Tensor | None = None,
+                           precision="fp32c", ckpt_every: int = 0, stream=None,
+                           energy="initial", dim: int = 3, integrator="euler") -> None:
+        """lddmm_shoot_grad_noalloc: the loss and dL/dp0 of shoot_grad into the
+        caller's grad [N,3], out3 [3] (and q1), with the library's fixed device
+        scratch as the workspace (the library allocates nothing)."""
+        n = q0.shape[0]
+        prm = make_params(n, T, sigma, lam, precision, ckpt_every, energy, dim, integrator)
+        if out3.dtype != torch.float64 or out3.numel() < 3 or not out3.is_cuda:
+            raise ValueError("out3 must be a float64 CUDA tensor of at least 3 elements")
+        _check(lib().lddmm_shoot_grad_noalloc(
+            self._h, ctypes.byref(prm), self._pts(q0, "q0", n), self._pts(p0, "p0", n),
+            self._pts(target, "target", n), out3.data_ptr(), self._pts(grad, "grad", n),
+            self._pts(q1, "q1", n) if q1 is not None else None, _stream(stream)), self._h)
 
     def solve(self, q0: torch.Tensor, target: torch.Tensor, T: int, sigma: float, lam: float,
               precision="fp32c", p0: torch.Tensor | None = None, ckpt_every: int = 0,

@@ -100,6 +100,8 @@ def test_calls_without_a_context_are_rejected_on_the_host(lib):
                                                        None, None),
         "lddmm_shoot_grad_all": lambda: L.lddmm_shoot_grad_all(None, P, fake, fake, fake, fake,
                                                                fake, None, None, None, None),
+        "lddmm_shoot_grad_noalloc": lambda: L.lddmm_shoot_grad_noalloc(None, P, fake, fake, fake,
+                                                                       fake, fake, None, None),
         "lddmm_velocity": lambda: L.lddmm_velocity(None, P, fake, fake, 5, fake, fake, None),
         "lddmm_flow": lambda: L.lddmm_flow(None, P, fake, fake, 5, fake, fake, None, None, None),
     }
