@@ -11,10 +11,14 @@ GPU parity tests compare against:
   ellipsoid4096 the 4096-landmark ellipsoid registration, T = 40: the oracle's
                 own L-BFGS run (Alg. 1 steps (e)-(f)) for 200 iterations from
                 p0 = 0, with q(1), the velocity v0 = K(q0) p0 (eq. 2's Hp) at
-                the solution and the (loss, |g|) trace
+                the solution and the (loss, |g|) trace; and the same run with
+                compensated sums (keys ending in _c), whose distance from the
+                first is the spread of the result under rounding alone
   serving8      the first 8 jobs of the seeded serving stream (seeds
                 40000 + j, N log-uniform in [500, 8000]), T = 40: the oracle's
                 L-BFGS run for 100 iterations each, as above
+  serving8_spread  the same 8 solves with compensated sums, added to the
+                serving8 record (keys ending in _c)
 
 Usage:  python tests/golden/make_workload_goldens.py [target ...] [--threads K]
 (several minutes to tens of minutes per target on a few host cores; the
@@ -66,9 +70,9 @@ def make_blobs65536() -> None:
     log(f"blobs65536: loss {g['loss']:.17g} H0 {g['H0']:.17g} H(q1,p1) {HT:.17g}")
 
 
-def solve_record(pb, settings) -> dict:
+def solve_record(pb, settings, compensated: bool = False) -> dict:
     opts = oracle.SolveOpts(max_iter=settings["max_iter"], gtol=settings["gtol"])
-    r = oracle.solve(pb.q0, pb.target, pb.sigma, pb.lam, pb.T, opts)
+    r = oracle.solve(pb.q0, pb.target, pb.sigma, pb.lam, pb.T, opts, compensated=compensated)
     q1 = oracle.shoot_forward(pb.q0, r["p0"], pb.sigma, pb.T)["q1"]
     v0 = oracle.pair_forward(pb.q0, r["p0"], pb.sigma)[1]
     return dict(n=pb.n, T=pb.T, sigma=pb.sigma, lam=pb.lam, seed=pb.seed,
@@ -82,8 +86,17 @@ def make_ellipsoid4096() -> None:
     pb = synth.ellipsoid_warp()
     log(f"ellipsoid4096: solve, N={pb.n} T={pb.T} {SOLVE_ELLIPSOID}")
     rec = solve_record(pb, SOLVE_ELLIPSOID)
-    np.savez(path("ellipsoid4096_solve200"), **rec)
     log(f"ellipsoid4096: loss {rec['loss']:.17g} iters {rec['iters']} fevals {rec['fevals']}")
+    # the same solve with Neumaier-compensated pair sums: it differs from the
+    # first only in rounding, so its distance from it after 200 iterations is
+    # the spread that rounding alone gives this (unconverged) optimiser path
+    log("ellipsoid4096: the same solve with compensated sums")
+    rc = solve_record(pb, SOLVE_ELLIPSOID, compensated=True)
+    for k in ("loss", "q1", "v0", "p0", "trace", "iters", "fevals"):
+        rec[k + "_c"] = rc[k]
+    np.savez(path("ellipsoid4096_solve200"), **rec)
+    log(f"ellipsoid4096 (compensated): loss {rc['loss']:.17g} iters {rc['iters']} "
+        f"fevals {rc['fevals']}")
 
 
 def make_serving8() -> None:
@@ -98,13 +111,29 @@ def make_serving8() -> None:
     np.savez(path("serving8_solve100"), jobs=SERVING_JOBS, **recs)
 
 
+def make_serving8_spread() -> None:
+    """The same 8 solves with compensated sums, added to the stored record
+    (keys job{j}_*_c): the spread of each job's result under rounding alone."""
+    old = dict(np.load(path("serving8_solve100")))
+    for j in range(SERVING_JOBS):
+        pb = synth.serving_job(j)
+        assert int(old[f"job{j}_n"]) == pb.n
+        log(f"serving job {j}: compensated solve, N={pb.n} T={pb.T} {SOLVE_SERVING}")
+        r = solve_record(pb, SOLVE_SERVING, compensated=True)
+        for k in ("loss", "q1", "v0", "p0", "iters", "fevals"):
+            old[f"job{j}_{k}_c"] = r[k]
+        log(f"serving job {j} (compensated): loss {r['loss']:.17g}")
+    np.savez(path("serving8_solve100"), **old)
+
+
 TARGETS = {"blobs65536": make_blobs65536, "ellipsoid4096": make_ellipsoid4096,
-           "serving8": make_serving8}
+           "serving8": make_serving8, "serving8_spread": make_serving8_spread}
 
 
 def main() -> None:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("targets", nargs="*", default=list(TARGETS))
+    ap.add_argument("targets", nargs="*", default=["blobs65536", "ellipsoid4096", "serving8",
+                                                   "serving8_spread"])
     ap.add_argument("--threads", type=int, default=os.cpu_count() or 1)
     a = ap.parse_args()
     oracle.set_threads(a.threads)
