@@ -208,11 +208,17 @@ struct Job {
   double* ckpt_state(int seg) const { return ckpt + (size_t)seg * 6 * p.n; }
 };
 
+// The launch plan of a problem (the workspace layout depends on its S).
+Plan plan_for(const lddmm_params& p) {
+  Plan plan = make_plan(p.n, target_waves());
+  if (!plan_overridden()) widen_plan(plan, p.precision, p.integrator == LDDMM_RK4);
+  return plan;
+}
+
 Job make_job(const lddmm_params& p, void* ws) {
   Job j{};
   j.p = p;
-  j.plan = make_plan(p.n, target_waves());
-  if (!plan_overridden()) widen_plan(j.plan, p.precision, p.integrator == LDDMM_RK4);
+  j.plan = plan_for(p);
   j.sc = make_scales(p.sigma, p.T);
   j.L = make_layout(p, j.plan);
   j.ws = ws;
@@ -314,8 +320,7 @@ lddmm_status begin(lddmm_ctx* ctx, const lddmm_params* params, Job* job, size_t 
   if (!ctx) return fail(nullptr, LDDMM_EINVAL, "ctx is NULL");
   lddmm_status st = check_params(ctx, params);
   if (st != LDDMM_OK) return st;
-  const Plan plan = make_plan(params->n, target_waves());
-  const Layout L = make_layout(*params, plan);
+  const Layout L = make_layout(*params, plan_for(*params));
   st = ensure_ws(ctx, L.total + a256(extra));
   if (st != LDDMM_OK) return st;
   HIP_TRY(ctx, hipSetDevice(ctx->device), "hipSetDevice");
@@ -450,7 +455,7 @@ lddmm_status lddmm_workspace_size(const lddmm_params* params, size_t* bytes) {
   lddmm_status st = check_params(nullptr, params);
   if (st != LDDMM_OK) return st;
   if (!bytes) return fail(nullptr, LDDMM_EINVAL, "bytes is NULL");
-  *bytes = make_layout(*params, make_plan(params->n, target_waves())).total;
+  *bytes = make_layout(*params, plan_for(*params)).total;
   return LDDMM_OK;
 }
 
@@ -490,7 +495,7 @@ lddmm_status lddmm_shoot_grad_noalloc(lddmm_ctx* ctx, const lddmm_params* params
     return fail(ctx, LDDMM_EINVAL, "q0, p0, target, out3 and grad must not be NULL");
   lddmm_status st = check_params(ctx, params);
   if (st != LDDMM_OK) return st;
-  const Layout L = make_layout(*params, make_plan(params->n, target_waves()));
+  const Layout L = make_layout(*params, plan_for(*params));
   if (L.total > kScratchBytes)
     return fail(ctx, LDDMM_ENOMEM,
                 "workspace of %zu bytes exceeds the fixed scratch of %zu bytes of "
