@@ -152,6 +152,18 @@ def measured_ceilings(iters: int = 40000, reps: int = 5) -> dict:
         if rc != 0:
             raise RuntimeError(f"rate probe {name} failed: hipError {rc}")
         out[name + "_per_s"] = round(r.value, 1)
+    # FP32 MFMA (16x16x4: 16 FMAs per lane) alone, and 4 MFMAs interleaved with
+    # 28 VALU FMAs per round: whether the matrix cores' work overlaps the VALU's
+    mf, mix = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    for kind, r in ((5, mf), (6, mix)):
+        rc = lib.rate_probe_run(kind, 2048, iters // 4, reps, ctypes.byref(r))
+        if rc != 0:
+            raise RuntimeError(f"rate probe {kind} failed: hipError {rc}")
+    out["mfma_f32_tflops"] = round(mf.value * 16 * 2 / 1e12, 2)
+    t_alone = 4 / mf.value + 28 / out["fp32_fma_vgpr_per_s"]
+    out["mfma_valu_mix"] = {"round_time_vs_sum_of_alone": round((1 / mix.value) / t_alone, 3),
+                            "mfma_tflops": round(mix.value * 4 * 16 * 2 / 1e12, 2),
+                            "valu_fma_tflops": round(mix.value * 28 * 2 / 1e12, 2)}
     for name in ("fp32_fma_vgpr", "fp32_fma_sgpr", "fp64_fma"):
         out[name + "_tflops"] = round(2 * out[name + "_per_s"] / 1e12, 2)
     # in units of one wave64 instruction per SIMD every 4 cycles (256 CUs, 2.4 GHz)

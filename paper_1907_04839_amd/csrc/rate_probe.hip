@@ -9,6 +9,12 @@
 //   kind 2  v_exp_f32 (2^x, the Gaussian of every pair)
 //   kind 3  v_fma_f64
 //   kind 4  v_mul_f32 with VGPR operands
+//   kind 5  v_mfma_f32_16x16x4_f32 (4 independent accumulators per wave);
+//           the rate counts one lane-operation per lane per MFMA (an MFMA is
+//           16 x 16 x 4 = 1024 FMAs, i.e. 16 per lane)
+//   kind 6  the same 4 MFMAs per round interleaved with 28 independent FP32
+//           FMAs with VGPR operands; the rate counts one per lane per round,
+//           to compare with kinds 0 and 5 run alone
 //
 // Each lane runs 8 independent dependency chains (enough to cover the ALU
 // latency) for `iters` rounds; a launch has 8 waves per SIMD of the chip.
@@ -97,16 +103,62 @@ __global__ __launch_bounds__(kBlock) void k_mul_v(const float* __restrict__ bc, 
   out[t] = s;
 }
 
+using F4 = float __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kBlock) void k_mfma(const float* __restrict__ bc, int iters,
+                                                 float* __restrict__ out) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const float a = bc[2 * t] + 1.0f, b = bc[2 * t + 1] + 0.5f;
+  F4 c0 = {0, 0, 0, 0}, c1 = c0, c2 = c0, c3 = c0;
+#pragma unroll 2
+  for (int it = 0; it < iters; ++it) {
+    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c1, 0, 0, 0);
+    c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c2, 0, 0, 0);
+    c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c3, 0, 0, 0);
+  }
+  const F4 c = c0 + c1 + c2 + c3;
+  out[t] = c[0] + c[1] + c[2] + c[3];
+}
+
+__global__ __launch_bounds__(kBlock) void k_mfma_valu(const float* __restrict__ bc, int iters,
+                                                      float* __restrict__ out) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const float a = bc[2 * t] + 1.0f, b = bc[2 * t + 1] + 0.5f;
+  F4 c0 = {0, 0, 0, 0}, c1 = c0, c2 = c0, c3 = c0;
+  float v[7];
+  for (int k = 0; k < 7; ++k) v[k] = 0.25f * (float)(k + 1) + 1e-3f * (float)threadIdx.x;
+#pragma unroll 2
+  for (int it = 0; it < iters; ++it) {
+    c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c0, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] = fmaf(v[k], b, a);
+    c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c1, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] = fmaf(v[k], b, a);
+    c2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c2, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] = fmaf(v[k], b, a);
+    c3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c3, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) v[k] = fmaf(v[k], b, a);
+  }
+  const F4 c = c0 + c1 + c2 + c3;
+  float s = c[0] + c[1] + c[2] + c[3];
+  for (int k = 0; k < 7; ++k) s += v[k];
+  out[t] = s;
+}
+
 }  // namespace
 
 extern "C" {
 
-// Runs probe `kind` (0-4) with `iters` rounds of 8 chains per lane on a grid
+// Runs probe `kind` (0-6) with `iters` rounds of 8 chains per lane on a grid
 // of `blocks` workgroups of 256 threads, `reps` timed launches after one
 // warm-up; writes the lane-operations per second (one FMA, multiply or exp
 // per lane per chain step) to *rate.  Returns a hipError_t (0 = success).
 int rate_probe_run(int kind, int blocks, int iters, int reps, double* rate) {
-  if (kind < 0 || kind > 4 || blocks < 1 || iters < 1 || reps < 1 || !rate) return 1;
+  if (kind < 0 || kind > 6 || blocks < 1 || iters < 1 || reps < 1 || !rate) return 1;
   const size_t threads = (size_t)blocks * kBlock;
   float *bc = nullptr, *out = nullptr;
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -121,7 +173,9 @@ int rate_probe_run(int kind, int blocks, int iters, int reps, double* rate) {
       case 1: k_fma_s<<<blocks, kBlock>>>(0.999f, 1e-3f, iters, out); break;
       case 2: k_exp<<<blocks, kBlock>>>(iters, out); break;
       case 3: k_fma64<<<blocks, kBlock>>>(bc, iters, out); break;
-      default: k_mul_v<<<blocks, kBlock>>>(bc, iters, out); break;
+      case 4: k_mul_v<<<blocks, kBlock>>>(bc, iters, out); break;
+      case 5: k_mfma<<<blocks, kBlock>>>(bc, iters, out); break;
+      default: k_mfma_valu<<<blocks, kBlock>>>(bc, iters, out); break;
     }
   };
   if (e == hipSuccess) {
@@ -136,8 +190,9 @@ int rate_probe_run(int kind, int blocks, int iters, int reps, double* rate) {
   if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
   float ms = 0.0f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+  const int per_round = kind == 5 ? 4 : kind == 6 ? 1 : kChains;
   if (e == hipSuccess)
-    *rate = (double)threads * iters * kChains * reps / (ms * 1e-3);
+    *rate = (double)threads * iters * per_round * reps / (ms * 1e-3);
   for (hipEvent_t v : ev)
     if (v) (void)hipEventDestroy(v);
   if (bc) (void)hipFree(bc);
