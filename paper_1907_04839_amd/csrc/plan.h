@@ -77,42 +77,31 @@ inline Plan make_plan(int n, int target_waves) {
   return p;
 }
 
-// Wider workgroups for the 8 x 8 plans (N from about 900 to 16384), where a
-// launch has 2 or fewer workgroups per CU: with 12 (or 16) waves each, two
-// resident workgroups fill more of a CU's wave slots than two of 8, and each
-// wave's j range is shorter.  The best width depends on the registers of the
-// kernel instance and was measured per precision and kind of step (ms per
-// loss+gradient evaluation, widths forward/adjoint vs 8/8): FP32-compensated
-// 12/12 (N = 4096: 1.308 vs 1.348; 1847: 0.661 vs 0.676; 16384 with T = 100:
-// 31.7 vs 32.5; planar 4096: 1.100 vs 1.125), FP32 16/16 (4096: 1.229 vs
-// 1.303), FP64 12/8 (4096: 2.375 vs 2.416; planar: 2.048 vs 2.106).  Other
-// widths were slower: 10 and 14 leave the four SIMDs unevenly loaded, 16
-// fits one FP32-compensated adjoint workgroup per CU, 12 one FP64 adjoint.
-// Runge-Kutta stage kernels hold more registers and keep 8/8 where
-// workgroups share CUs (12/12: 1.494 vs 1.382 ms in FP32-compensated, 3.06
-// vs 2.43 in FP64).  The 8 x 2 plans of N from about 65000 to 116000 (eight
-// workgroups per CU in turn; the 8 x 2 plans of N = 144-271 stay 8/8) gain too
-// in FP32 modes, where two 12-wave workgroups divide the turns evenly:
-// N = 65536 FP32-compensated 12/12 238.4 vs 242.3 ms, FP32 16/16 233.2 vs
-// 240.6; FP64 12/8 585 vs 583 (kept at 8/8).  The 8 x 4 and 8 x 3 plans
-// (N from 272 to 911, and from about 16400 to 65000) take 12/12 in both
-// FP32 modes: FP32-compensated N = 600 0.58 vs 0.647 ms, 800 0.637 vs 0.722,
-// 32768 (T = 10) 12.05 vs 12.23, 50000 (T = 4) 12.12 vs 12.29; FP32 N = 800
-// 0.618 vs 0.706, 32768 11.82 vs 12.12, 50000 11.89 vs 12.19 (16/16 was
-// erratic at N = 600 and slower in the FP32-compensated adjoint at 32768).
-// FP64 gains from width only while a launch has at most one workgroup per CU
-// (no workgroups compete for a CU's registers): 12/12 at N = 350 0.764 vs
-// 0.886 ms, N = 800 0.955 vs 1.124 and N = 1847 (232 workgroups) 0.925 vs
-// 0.946, and 16/16 better still (0.726, 0.894, 0.919), but at N = 32768 and
-// 50000 12/12 was 10-23 % slower and 12/8 equal to 8/8.  Runge-Kutta stage
-// kernels likewise gain where a launch has at most one workgroup per CU
-// (T = 10): FP32-compensated 12/12 N = 800 0.662 vs 0.800 ms, FP64 16/16
-// N = 350 0.757 vs 0.971 and N = 800 0.917 vs 1.207; FP32 stages were not
-// measured and keep 8/8.  The sum order within a workgroup follows the
-// width, so results change at rounding level.
-// The workgroup widths measured fastest for the pair kernels of a precision
-// mode and kind of step (rk: Runge-Kutta stages), applied to the plans of 8
-// waves and 8, 4, 3 or 2 j-chunks; other plans are left as they are.
+// Wider workgroups for the plans of 8 waves and 8, 4, 3 or 2 j-chunks.  The
+// best width depends on the kernel instance's registers and LDS and on how
+// many workgroups share a CU.  Measured per precision mode and kind of step
+// (ms per loss+gradient evaluation; widths forward/adjoint 12/12, 8/8, 16/16;
+// Euler unless marked):
+//   FP32-compensated: N = 4096 1.298, 1.351, 1.451; 16384 (T = 4) 1.298,
+//     1.322, 1.585; 65536 (T = 3) 14.38, 14.78, 17.35; 800 (T = 10) 0.167,
+//     0.187, 0.163; Runge-Kutta N = 4096 (T = 10) 1.317, 1.378, 1.469
+//     -> 12/12 everywhere.  Its 16-wave workgroups, like the FP64 ones, hold
+//     72 KiB of LDS for the wave combine and were slow wherever workgroups
+//     share a CU.
+//   FP32 (16/16 first): N = 4096 1.213, 1.241, 1.296; 32768 (T = 2) 2.384,
+//     2.438, 2.446; 65536 13.93, 14.17, 14.33; 800 0.156, 0.162, 0.183
+//     -> 16/16; Runge-Kutta N = 4096 1.288, 1.269, 1.320; 800 (T = 3) 0.192,
+//     0.199, 0.227 -> 12/12, or 16/16 where a launch has at most one
+//     workgroup per CU.
+//   FP64: N = 4096 2.314, 2.415, 2.694; 16384 2.845, 2.913, 3.310; 65536
+//     33.58, 34.43, 41.39; with at most one workgroup per CU (16/16 first)
+//     N = 800 0.245, 0.261, 0.312 and 1847 0.938, 0.952, 0.994 -> 16/16 there,
+//     else 12/12; Runge-Kutta N = 4096 8/8 2.356 against 2.573 (12/12) ->
+//     unwidened unless at most one workgroup per CU (16/16: N = 800 0.286
+//     against 0.350 at 8/8).
+// Widths 10 and 14 leave the four SIMDs unevenly loaded (measured slower).
+// The sum order within a workgroup follows the width, so results change at
+// rounding level.
 inline void widen_plan(Plan& p, int mode, bool rk) {
   constexpr int kCUs = 256;   // MI355X
   if (p.W != 8) return;
@@ -124,18 +113,18 @@ inline void widen_plan(Plan& p, int mode, bool rk) {
   const bool one_per_cu = p.nb * p.S <= kCUs;
   int wf = 8, wa = 8;
   if (rk) {
-    // Runge-Kutta stages, only where no workgroups compete for a CU
-    if (!one_per_cu) return;
-    if (mode == kFP32Comp) { wf = 12; wa = 12; }
-    else if (mode == kFP64) { wf = 16; wa = 16; }
-    else return;
+    if (mode == kFP32Comp) { wf = wa = 12; }
+    else if (mode == kFP32) { wf = wa = one_per_cu ? 16 : 12; }
+    else if (mode == kFP64) {
+      if (!one_per_cu) return;   // 12 or 16 waves measured slower there
+      wf = wa = 16;
+    }
   } else if (mode == kFP32Comp) {
-    wf = 12; wa = 12;
+    wf = wa = 12;
   } else if (mode == kFP32) {
-    wf = wa = (p.S == 8 || p.S == 2) ? 16 : 12;
+    wf = wa = 16;
   } else if (mode == kFP64) {
-    if (one_per_cu) { wf = 16; wa = 16; }
-    else if (p.S == 8) { wf = 12; wa = 8; }
+    wf = wa = one_per_cu ? 16 : 12;
   }
   p.W = wf;
   p.wchunk = (p.chunk + wf - 1) / wf;

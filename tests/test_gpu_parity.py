@@ -105,10 +105,10 @@ def test_gradient_matches_oracle(gpu_ctx, orc_mt, mode, n, T):
 # smallest N and at a ragged N inside its range (N and the per-wave j range not
 # multiples of 64): (1,1) 1 16 31, (2,1) 32 40 47, (2,2) 48 56 63, (4,1) 64 72 79,
 # (4,2) 80 104 127, (8,1) 128 136 143, (8,2) 144 208 271, (8,3) 272 336 399,
-# (8,4) 400 911 19089, (8,8) 912 9800.  The (8,8) plans run wider workgroups
-# (forward/adjoint waves): FP32-compensated 12/12, FP32 16/16, FP64 12/8; the
-# (8,4) and (8,3) plans 12/12 in both FP32 modes; FP64 16/16 wherever a launch
-# has at most 256 workgroups (e.g. 272-399, 911).
+# (8,4) 400 911 19089, (8,8) 912 9800.  The (8,8), (8,4) and (8,3) plans run
+# wider workgroups (forward/adjoint waves): FP32-compensated 12/12, FP32 16/16,
+# FP64 12/12, or 16/16 wherever a launch has at most 256 workgroups (e.g.
+# 272-399, 911).
 PLAN_SWEEP = [1, 16, 31, 32, 40, 47, 48, 56, 63, 64, 72, 79, 80, 104, 127, 128, 136, 143, 144,
               208, 271, 272, 336, 399, 400, 911, 912, 9800, 19089]
 

@@ -62,12 +62,11 @@ def test_rk4_gradients_match_oracle(gpu_ctx, orc_mt, mode, n, T, ckpt, energy):
     assert_gates(errs, mode, TOL[mode])
 
 
-# Runge-Kutta stage kernels take their own workgroup widths (widened only in
-# launches of at most one workgroup per CU): sizes at the ends of the (8,2)
-# plans (144, 271: not widened, fewer than 16 j per wave), the (8,3) plan at
-# 350 (FP64 16/16), the (8,4) plan at 800 (FP32-compensated 12/12, FP64 16/16),
-# and the (8,8) plan at 1847 (FP32-compensated 12/12, FP64 16/16: 232
-# workgroups) and 4096 (512 workgroups: stage kernels stay 8/8).
+# Runge-Kutta stage kernels take their own workgroup widths: sizes at the ends
+# of the (8,2) plans (144, 271: not widened, fewer than 16 j per wave), the
+# (8,3) plan at 350 and the (8,4) plan at 800 (FP32-compensated 12/12, FP32 and
+# FP64 16/16), and the (8,8) plan at 1847 (232 workgroups: the same widths) and
+# 4096 (512 workgroups: FP32-compensated and FP32 12/12, FP64 8/8).
 RK4_PLAN_SWEEP = [144, 271, 350, 800, 1847, 4096]
 
 
