@@ -197,6 +197,24 @@ def roofline(n, kt, traffic=None, precision="fp32c", flops=FLOPS_PER_PAIR):
     return out
 
 
+def issue_ceiling(pairs_per_s: float, precision: str):
+    """The evaluation's ceiling in pair-interactions/s from the rates measured on
+    the chip and the pair loops' instruction counts: every VALU instruction at
+    the measured rate of FP32 FMAs with VGPR operands (the fastest non-packed
+    form; SGPR-operand instructions issue slower, so this bound is high) and
+    the one v_exp_f32 per pair at its measured rate, not overlapped.  FP32 modes
+    only (the FP64 loops compute their own 2^x)."""
+    if precision == "fp64" or not CEILINGS:
+        return None
+    valu = CEILINGS["fp32_fma_vgpr_per_s"]
+    exp = CEILINGS["exp_f32_per_s"]
+    t = sum((VALU_PER_PAIR[k] - 1) / valu + 1 / exp for k in ("fwd", "adj"))
+    ceiling = 2 / t
+    return {"pairs_per_s": round(ceiling, 1), "frac": round(pairs_per_s / ceiling, 4),
+            "valu_per_pair": {k: VALU_PER_PAIR[k] - 1 for k in ("fwd", "adj")},
+            "exp_per_pair": 1}
+
+
 def measure(ctx, name: str, precision: str, steps: int, warmup: int, ckpt_every: int = 0,
             events: bool = True):
     """pair-interactions/s of one workload (steps timed after warmup), per-step
@@ -224,6 +242,7 @@ def measure(ctx, name: str, precision: str, steps: int, warmup: int, ckpt_every:
     # algorithmic flops (recompute launches not counted) over the step time
     flops = (FLOPS_PER_PAIR["fwd"] + FLOPS_PER_PAIR["adj"]) * pb.T * float(pb.n) ** 2
     out["whole_eval_alu_frac"] = round(flops / (ms * 1e-3) / (PEAK_TFLOPS[precision] * 1e12), 4)
+    out["issue_ceiling"] = issue_ceiling(out["pairs_per_s"], precision)
     log(f"[bench] {pb.name} {precision}: {out['pairs_per_s']:.4g} pair-interactions/s, "
         f"{ms:.3f} ms/step; adj {kt['adj_us']:.2f} us, fwd {kt['fwd_us']:.2f} us per launch; "
         f"frac {out['roofline']['frac']}, whole evaluation {out['whole_eval_alu_frac']}")
@@ -639,12 +658,14 @@ def main():
             for prec in ("fp32", "fp32c", "fp64"):
                 if prec == args.precision:
                     modes[prec] = {k: head[k] for k in ("pairs_per_s", "ms_per_step",
-                                                        "whole_eval_alu_frac", "roofline")}
+                                                        "whole_eval_alu_frac", "issue_ceiling",
+                                                        "roofline")}
                     continue
                 k = max(2, min(args.steps, 3 if pb.n >= 65536 else 10))
                 m = measure(ctx, args.workload, prec, k, 1, ckpt, events=False)
                 modes[prec] = {k2: m[k2] for k2 in ("pairs_per_s", "ms_per_step",
-                                                     "whole_eval_alu_frac", "roofline")}
+                                                     "whole_eval_alu_frac", "issue_ceiling",
+                                                     "roofline")}
             extra["modes"] = modes
             # the 4096-landmark ellipsoid registration: evaluation rate, modes, full solve
             if args.workload != "ellipsoid4096":
@@ -698,6 +719,7 @@ def main():
                    "pairs_per_step": head["pairs_per_step"]},
         "roofline": head["roofline"],
         "whole_eval_alu_frac": head["whole_eval_alu_frac"],
+        "issue_ceiling": head["issue_ceiling"],
         "kernel_us": head["kernel_us"],
         "cpu_baseline": cpu,
     }
