@@ -74,17 +74,45 @@ __device__ __forceinline__ void block_sum2(double s, double t, double* red, doub
 
 // Each thread owns elements k = threadIdx.x + j kThreads of every vector and
 // sums its products in increasing k, so fusing passes below changes no bit.
+// A pass visits the thread's elements in that order, kBatch at a time: the
+// loads of a batch (NV source vectors) are all issued before the first of its
+// elements is used.  One workgroup serves a whole problem, so a pass that waited
+// for each element's loads in turn would take one memory latency per element.
+// Only the thread's own elements are read and written, so reading a batch ahead
+// of the batch's stores changes nothing.
+constexpr int kBatch = 8;
+
+template <int NV, typename F>
+__device__ __forceinline__ void own_elems(int m, const double* const (&src)[NV], F&& f) {
+  for (int k0 = threadIdx.x; k0 < m; k0 += kBatch * kThreads) {
+    double v[kBatch][NV];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int k = k0 + u * kThreads;
+#pragma unroll
+      for (int c = 0; c < NV; ++c) v[u][c] = k < m ? src[c][k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int k = k0 + u * kThreads;
+      if (k < m) f(k, v[u]);
+    }
+  }
+}
+
 __device__ __forceinline__ double block_dot(const double* __restrict__ a,
                                             const double* __restrict__ b, int m, double* red) {
   double s = 0.0;
-  for (int k = threadIdx.x; k < m; k += kThreads) s += a[k] * b[k];
+  const double* src[2] = {a, b};
+  own_elems<2>(m, src, [&](int, const double* v) { s += v[0] * v[1]; });
   return block_sum(s, red);
 }
 
 // x_t = x + a d without FMA contraction (the same rounding as x + a*d on a host)
 __device__ __forceinline__ void trial_point(const LbfgsBufs& B, double a) {
-  for (int k = threadIdx.x; k < B.m3; k += kThreads)
-    B.xt[k] = __dadd_rn(B.x[k], __dmul_rn(a, B.d[k]));
+  const double* src[2] = {B.x, B.d};
+  own_elems<2>(B.m3, src,
+               [&](int k, const double* v) { B.xt[k] = __dadd_rn(v[0], __dmul_rn(a, v[1])); });
 }
 
 // Safeguarded cubic step between (a0,f0,d0) and (a1,f1,d1).
@@ -106,7 +134,8 @@ __device__ double cubic_step(double a0, double f0, double d0, double a1, double 
 // job reports them without another evaluation.
 __device__ __forceinline__ void snapshot(const LbfgsBufs& B) {
   if (!B.q1t) return;
-  for (int k = threadIdx.x; k < B.m3; k += kThreads) B.q1a[k] = B.q1t[k];
+  const double* src[1] = {B.q1t};
+  own_elems<1>(B.m3, src, [&](int k, const double* v) { B.q1a[k] = v[0]; });
   if (threadIdx.x < 3) B.out3a[threadIdx.x] = B.ft[threadIdx.x];
 }
 
@@ -127,12 +156,13 @@ __device__ void new_direction(const LbfgsBufs& B, const LbfgsOpts& o, LbfgsState
   double gd, dd = 0.0;
   if (used == 0) {                               // steepest descent: d = -g
     double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < m3; k += kThreads) {
-      const double v = -B.g[k];
+    const double* src[1] = {B.g};
+    own_elems<1>(m3, src, [&](int k, const double* g) {
+      const double v = -g[0];
       B.d[k] = v;
-      a += B.g[k] * v;
+      a += g[0] * v;
       b += v * v;
-    }
+    });
     block_sum2(a, b, red, &gd, &dd);
   } else {
     double sy, yy;                               // H0 scaling from the newest pair
@@ -140,21 +170,21 @@ __device__ void new_direction(const LbfgsBufs& B, const LbfgsOpts& o, LbfgsState
       const double* Sn = Sv(0);
       const double* Yn = Yv(0);
       double a = 0.0, b = 0.0;
-      for (int k = threadIdx.x; k < m3; k += kThreads) {
-        a += Sn[k] * Yn[k];
-        b += Yn[k] * Yn[k];
-      }
+      const double* src[2] = {Sn, Yn};
+      own_elems<2>(m3, src, [&](int, const double* v) {
+        a += v[0] * v[1];
+        b += v[1] * v[1];
+      });
       block_sum2(a, b, red, &sy, &yy);
     }
     const double gamma = sy / yy;
     double acc = 0.0;                            // d = g, and S_0 . d
     {
-      const double* S0 = Sv(0);
-      for (int k = threadIdx.x; k < m3; k += kThreads) {
-        const double v = B.g[k];
-        B.d[k] = v;
-        acc += S0[k] * v;
-      }
+      const double* src[2] = {B.g, Sv(0)};
+      own_elems<2>(m3, src, [&](int k, const double* v) {
+        B.d[k] = v[0];
+        acc += v[1] * v[0];
+      });
     }
     for (int h = 0; h < used; ++h) {             // newest to oldest
       const double al = st.rho[slot(h)] * block_sum(acc, red);
@@ -163,12 +193,13 @@ __device__ void new_direction(const LbfgsBufs& B, const LbfgsOpts& o, LbfgsState
       const bool last = h + 1 == used;
       const double* Nx = last ? Yv(used - 1) : Sv(h + 1);   // the next inner product's vector
       acc = 0.0;
-      for (int k = threadIdx.x; k < m3; k += kThreads) {
-        double v = B.d[k] - al * Ys[k];
+      const double* src[3] = {B.d, Ys, Nx};
+      own_elems<3>(m3, src, [&](int k, const double* w) {
+        double v = w[0] - al * w[1];
         if (last) v *= gamma;
         B.d[k] = v;
-        acc += Nx[k] * v;
-      }
+        acc += w[2] * v;
+      });
     }
     for (int h = used - 1; h >= 0; --h) {         // oldest to newest
       const double beta = st.rho[slot(h)] * block_sum(acc, red);
@@ -177,24 +208,26 @@ __device__ void new_direction(const LbfgsBufs& B, const LbfgsOpts& o, LbfgsState
       const bool last = h == 0;
       const double* Nx = last ? B.g : Yv(h - 1);
       acc = 0.0;
-      for (int k = threadIdx.x; k < m3; k += kThreads) {
-        double v = B.d[k] + (al - beta) * Ss[k];
+      const double* src[3] = {B.d, Ss, Nx};
+      own_elems<3>(m3, src, [&](int k, const double* w) {
+        double v = w[0] + (al - beta) * w[1];
         if (last) v = -v;                        // the direction is -H g
         B.d[k] = v;
-        acc += Nx[k] * v;
-      }
+        acc += w[2] * v;
+      });
     }
     gd = block_sum(acc, red);
   }
   const bool restart = !(gd < 0.0);             // not a descent direction: restart
   if (restart) {
     double a = 0.0, b = 0.0;
-    for (int k = threadIdx.x; k < m3; k += kThreads) {
-      const double v = -B.g[k];
+    const double* src[1] = {B.g};
+    own_elems<1>(m3, src, [&](int k, const double* g) {
+      const double v = -g[0];
       B.d[k] = v;
-      a += B.g[k] * v;
+      a += g[0] * v;
       b += v * v;
-    }
+    });
     block_sum2(a, b, red, &gd, &dd);
   }
   const double a0 = (restart || used == 0) ? 1.0 / sqrt(dd) : 1.0;
@@ -222,19 +255,20 @@ __device__ void accept(const LbfgsBufs& B, const LbfgsOpts& o, LbfgsState& st, d
   double* Ss = B.S + (size_t)slot * m3;
   double* Ys = B.Y + (size_t)slot * m3;
   double a = 0.0, b = 0.0, gg = 0.0, xx = 0.0;
-  for (int k = threadIdx.x; k < m3; k += kThreads) {   // new pair, and x, g move to x_t, g_t
-    const double sv = B.xt[k] - B.x[k];
-    const double yv = B.gt[k] - B.g[k];
+  const double* src[4] = {B.xt, B.x, B.gt, B.g};
+  own_elems<4>(m3, src, [&](int k, const double* v) {   // new pair; x, g move to x_t, g_t
+    const double sv = v[0] - v[1];
+    const double yv = v[2] - v[3];
     Ss[k] = sv;
     Ys[k] = yv;
     a += sv * yv;
     b += yv * yv;
-    const double xv = B.xt[k], gv = B.gt[k];
+    const double xv = v[0], gv = v[2];
     B.x[k] = xv;
     B.g[k] = gv;
     gg += gv * gv;
     xx += xv * xv;
-  }
+  });
   snapshot(B);
   double sy, yy, gsq, xsq;
   block_sum2(a, b, red, &sy, &yy);
@@ -303,7 +337,8 @@ __device__ void step_body(const LbfgsBufs& B, LbfgsState* state, const LbfgsOpts
   if (threadIdx.x == 0) st.fevals += 1;
 
   if (st.phase == kInit) {
-    for (int k = threadIdx.x; k < m3; k += kThreads) B.g[k] = B.gt[k];
+    const double* src[1] = {B.gt};
+    own_elems<1>(m3, src, [&](int k, const double* v) { B.g[k] = v[0]; });
     snapshot(B);
     __syncthreads();
     const double gg = block_dot(B.g, B.g, m3, red);
