@@ -12,15 +12,16 @@ from conftest import to_dev
 pytestmark = pytest.mark.gpu
 
 
-def _pair(ctx, pb, mode, ckpt=0):
+def _pair(ctx, pb, mode, ckpt=0, **kw):
     import torch
     q0, p0, x = to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target)
-    ref = ctx.shoot_grad(q0, p0, x, pb.T, pb.sigma, pb.lam, precision=mode, ckpt_every=ckpt)
+    ref = ctx.shoot_grad(q0, p0, x, pb.T, pb.sigma, pb.lam, precision=mode, ckpt_every=ckpt,
+                         **kw)
     grad = torch.full_like(q0, float("nan"))
     out3 = torch.full((3,), float("nan"), dtype=torch.float64, device=q0.device)
     q1 = torch.full_like(q0, float("nan"))
     ctx.shoot_grad_noalloc(q0, p0, x, pb.T, pb.sigma, pb.lam, grad, out3, q1, precision=mode,
-                           ckpt_every=ckpt)
+                           ckpt_every=ckpt, **kw)
     torch.cuda.synchronize()
     return ({"out3": torch.stack([ref.loss, ref.H0, ref.mismatch]).cpu().numpy(),
              "grad": ref.grad.cpu().numpy(), "q1": ref.q1.cpu().numpy()},
@@ -45,6 +46,60 @@ def test_noalloc_with_checkpoints(gpu_ctx):
     ref, got = _pair(gpu_ctx, pb, "fp32c", ckpt=4)
     for k in ("out3", "grad", "q1"):
         assert np.array_equal(got[k], ref[k]), k
+
+
+# the other kinds of evaluation share the entry point: Runge-Kutta stages (with
+# their stage records and accumulators in the scratch), the planar pair loops,
+# and the energy taken at t = 1 (its extra buffers)
+@pytest.mark.parametrize("variant,mode", [("rk4", "fp32c"), ("planar", "fp32c"),
+                                          ("energy_final", "fp64")])
+def test_noalloc_variants_match_shoot_grad(gpu_ctx, variant, mode):
+    pb = synth.random_problem(7110, 1100, T=5)
+    kw = {"rk4": dict(integrator="rk4"), "planar": dict(dim=2),
+          "energy_final": dict(energy="final")}[variant]
+    if variant == "planar":
+        pb = synth.planar(pb)
+    ref, got = _pair(gpu_ctx, pb, mode, ckpt=2 if variant == "rk4" else 0, **kw)
+    for k in ("out3", "grad", "q1"):
+        assert np.all(np.isfinite(got[k])), (variant, k)
+        assert np.array_equal(got[k], ref[k]), (variant, k)
+
+
+def test_noalloc_captured_in_a_graph(gpu_ctx):
+    """The callers it is for: captured once without any warm-up call (nothing
+    to allocate), replayed with other calls of the entry point, which reuse
+    the same scratch, between the replays; every replay is bitwise the eager
+    result."""
+    import torch
+    pb = synth.random_problem(7120, 1300, T=6)
+    q0, p0, x = to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target)
+    ref = gpu_ctx.shoot_grad(q0, p0, x, pb.T, pb.sigma, pb.lam, precision="fp32c")
+    torch.cuda.synchronize()
+    ref_g = ref.grad.cpu().numpy()
+    ref_o = torch.stack([ref.loss, ref.H0, ref.mismatch]).cpu().numpy()
+    grad = torch.zeros_like(q0)
+    out3 = torch.zeros(3, dtype=torch.float64, device=q0.device)
+    other = synth.random_problem(7121, 600, T=4)
+    oq, op, ox = to_dev(other.q0), to_dev(other.p0), to_dev(other.target)
+    og, oo = torch.empty_like(oq), torch.empty(3, dtype=torch.float64, device=oq.device)
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        gpu_ctx.shoot_grad_noalloc(q0, p0, x, pb.T, pb.sigma, pb.lam, grad, out3,
+                                   precision="fp32c", stream=s)
+    torch.cuda.synchronize()
+    for k in range(3):
+        grad.zero_()
+        out3.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(grad.cpu().numpy(), ref_g, err_msg=f"replay {k}")
+        np.testing.assert_array_equal(out3.cpu().numpy(), ref_o, err_msg=f"replay {k}")
+        with torch.cuda.stream(s):     # another problem through the same scratch
+            gpu_ctx.shoot_grad_noalloc(oq, op, ox, other.T, other.sigma, other.lam, og, oo,
+                                       precision="fp64", stream=s)
+        torch.cuda.synchronize()
 
 
 def test_noalloc_rejects_problems_beyond_the_scratch(gpu_ctx):
