@@ -76,7 +76,7 @@ def test_blobs65536_T50_precision_study(gpu_ctx, mode):
              grad=rel_err(host(r.grad), o["grad"]), grad_row=row_err(host(r.grad), o["grad"]))
     print(f"[precision blobs65536 T=50 {mode}] " + " ".join(f"{k}={v:.2e}" for k, v in e.items()),
           flush=True)
-    # FP32 with one running sum per wave over the wave's 2731-2732 j of 65536
+    # FP32 with one running sum per wave over the wave's 2048 j of 65536
     # (the launch plan's j split): expected to lose accuracy with N
     tol = {"fp64": 1e-12, "fp32c": 1e-5, "fp32": 1e-4}[mode]
     row_tol = {"fp64": ROW_TOL["fp64"], "fp32c": ROW_TOL["fp32c"], "fp32": 1e-3}[mode]
