@@ -200,10 +200,10 @@ def roofline(n, kt, traffic=None, precision="fp32c", flops=FLOPS_PER_PAIR):
 def issue_ceiling(pairs_per_s: float, precision: str):
     """The evaluation's ceiling in pair-interactions/s from the rates measured on
     the chip and the pair loops' instruction counts: every VALU instruction at
-    the measured rate of FP32 FMAs with VGPR operands (the fastest non-packed
-    form; SGPR-operand instructions issue slower, so this bound is high) and
-    the one v_exp_f32 per pair at its measured rate, not overlapped.  FP32 modes
-    only (the FP64 loops compute their own 2^x)."""
+    the measured rate of FP32 FMAs with VGPR operands (multiplies issue a little
+    faster, instructions with an SGPR operand much slower, so the bound is high)
+    and the one v_exp_f32 per pair at its measured rate, not overlapped.  FP32
+    modes only (the FP64 loops compute their own 2^x)."""
     if precision == "fp64" or not CEILINGS:
         return None
     valu = CEILINGS["fp32_fma_vgpr_per_s"]
