@@ -9,7 +9,7 @@ import pytest
 
 from paper_1907_04839_amd import synth
 
-from conftest import rel_err
+from conftest import rel_err, row_err
 
 pytestmark = pytest.mark.gpu
 
@@ -125,9 +125,10 @@ def test_fp64_server_matches_oracle_solver(orc_mt, gpu_ctx):
         q1o = orc_mt.shoot_forward(pb.q0, o["p0"], pb.sigma, T)["q1"]
         el = abs(r["loss"] - o["loss"]) / o["loss"]
         print(f"[serve fp64 n={pb.n}] iters {r['iters']}/{o['iters']} fevals "
-              f"{r['fevals']}/{o['fevals']} loss={el:.2e} q1={rel_err(q1g, q1o):.2e}", flush=True)
+              f"{r['fevals']}/{o['fevals']} loss={el:.2e} q1={rel_err(q1g, q1o):.2e} "
+              f"q1_row={row_err(q1g, q1o):.2e}", flush=True)
         assert r["iters"] == o["iters"] and r["fevals"] == o["fevals"]
-        assert el < 1e-10 and rel_err(q1g, q1o) < 1e-10
+        assert el < 1e-10 and rel_err(q1g, q1o) < 1e-10 and row_err(q1g, q1o) < 1e-10
         assert abs(r["avg_dist"] - o["avg_dist"]) < 1e-9 * o["avg_dist"]
 
 

@@ -7,7 +7,7 @@ import pytest
 
 from paper_1907_04839_amd import synth
 
-from conftest import rel_err, to_dev
+from conftest import rel_err, row_err, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -95,13 +95,13 @@ def test_ellipsoid4096_solver_trace_matches_oracle(gpu_ctx, orc_mt, mode):
     q1g = gpu_q1(gpu_ctx, pb, g["p0"])
     q1o = orc_mt.shoot_forward(pb.q0, o["p0"], pb.sigma, pb.T)["q1"]
     e = dict(loss=abs(g["loss"] - o["loss"]) / o["loss"], q1=rel_err(q1g, q1o),
-             p0=rel_err(g["p0"], o["p0"]), trace_loss=tr)
+             q1_row=row_err(q1g, q1o), p0=rel_err(g["p0"], o["p0"]), trace_loss=tr)
     print(f"[solve ellipsoid4096 {mode}] iters {g['iters']}/{o['iters']} fevals "
           f"{g['fevals']}/{o['fevals']} " + " ".join(f"{a}={b:.2e}" for a, b in e.items()),
           flush=True)
     tol = 1e-10 if mode == "fp64" else 1e-5
     assert g["iters"] == o["iters"]
-    assert e["trace_loss"] < tol and e["loss"] < tol and e["q1"] < tol
+    assert e["trace_loss"] < tol and e["loss"] < tol and e["q1"] < tol and e["q1_row"] < tol
 
 
 def test_solver_is_bitwise_reproducible(gpu_ctx):
