@@ -13,7 +13,7 @@ import pytest
 
 from paper_1907_04839_amd import synth
 
-from conftest import rel_err, to_dev
+from conftest import ROW_TOL, rel_err, row_err, to_dev
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -32,7 +32,9 @@ def test_precision_modes_against_oracle(gpu_ctx, orc_mt):
         errs[mode] = dict(loss=abs(r.loss.item() - o["loss"]) / abs(o["loss"]),
                           H0=abs(r.H0.item() - o["H0"]) / abs(o["H0"]),
                           q1=rel_err(r.q1.cpu().numpy(), o["q1"]),
-                          grad=rel_err(r.grad.cpu().numpy(), o["grad"]))
+                          q1_row=row_err(r.q1.cpu().numpy(), o["q1"]),
+                          grad=rel_err(r.grad.cpu().numpy(), o["grad"]),
+                          grad_row=row_err(r.grad.cpu().numpy(), o["grad"]))
         # the energy at the final state, H(q(1), p(1)), through the loss option
         rf = gpu_ctx.shoot_grad(to_dev(pb.q0), to_dev(pb.p0), to_dev(pb.target), T, pb.sigma,
                                 pb.lam, precision=mode, energy="final", want_q1=False)
@@ -40,8 +42,10 @@ def test_precision_modes_against_oracle(gpu_ctx, orc_mt):
         errs[mode]["HT"] = abs(rf.H0.item() - of["H0"]) / abs(of["H0"])
         print(f"[precision blobs65536 T={T} {mode}] " +
               " ".join(f"{k}={v:.2e}" for k, v in errs[mode].items()), flush=True)
-    assert max(errs["fp64"].values()) <= 1e-12
-    assert max(errs["fp32c"].values()) <= 1e-5
-    # one running FP32 sum over 4096 pairs per wave: expected to lose accuracy with N
-    assert max(errs["fp32"].values()) <= 1e-4
+    # FP32-naive: one running FP32 sum per wave over 2048 of the 65536 j (the
+    # plan's j split): expected to lose accuracy with N
+    for mode, tol, row_tol in (("fp64", 1e-12, ROW_TOL["fp64"]),
+                               ("fp32c", 1e-5, ROW_TOL["fp32c"]), ("fp32", 1e-4, 1e-3)):
+        for k, v in errs[mode].items():
+            assert v <= (row_tol if k.endswith("_row") else tol), (mode, k, v)
     assert errs["fp32c"]["grad"] <= errs["fp32"]["grad"]
