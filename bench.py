@@ -8,7 +8,7 @@ pair sums (Alg. 1 ComputeGradient).  It counts 2 T N^2 pair interactions
 
 Headline workload (`value`): the largest single-GPU configuration, 65536
 landmarks in two Gaussian blobs (centres 50 apart, sd 15), sigma 5, lambda 1,
-T = 50, FP32 pair sums with 64-pair tiles folded into FP64 (FP64 state, loss
+T = 50, FP32 pair sums with 72-pair tiles folded into FP64 (FP64 state, loss
 and adjoint state).  The same line carries the other precision modes at that
 size, the 4096-landmark ellipsoid registration (T = 40) with its full solve,
 the 16384-landmark sphere with checkpoints, the point flow, planar and

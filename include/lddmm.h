@@ -67,7 +67,7 @@ typedef enum {
  * the optimiser are FP64 in every mode. */
 typedef enum {
   LDDMM_FP32 = 0,          /* FP32 pair terms, one running FP32 sum per wave */
-  LDDMM_FP32_COMP = 1,     /* FP32 pair terms, FP32 sums of 64 pairs folded into FP64 */
+  LDDMM_FP32_COMP = 1,     /* FP32 pair terms, FP32 sums of 72 pairs folded into FP64 */
   LDDMM_FP64 = 2           /* FP64 throughout */
 } lddmm_precision;
 

@@ -1,5 +1,5 @@
 """Precision study on the 65536-landmark two-blob workload: one gradient in
-FP32 (one running sum per wave), FP32 compensated (64-pair tiles folded into
+FP32 (one running sum per wave), FP32 compensated (72-pair tiles folded into
 FP64) and FP64, each against the FP64 oracle on the full problem: loss, H0,
 q(1), the gradient, and the energy of the final state H(q(1), p(1)).
 
